@@ -1,0 +1,187 @@
+/*
+ * skolem.h -- C ABI of the MI355X (gfx950) library for counting Skolem,
+ * Langford and hooked Skolem pairings, after "Counting Skolem Sequences"
+ * (Assarpour, Bar-Noy, Liu; arXiv 1507.00315).
+ *
+ * Problems (Sec. 1.1, Sec. 1.2):
+ *   SK_SKOLEM   split {1..2n} into n pairs (a_k, a_k + k), k = 1..n.
+ *   SK_LANGFORD split {1..2n} into n pairs (a_k, a_k + k + 1): the two copies
+ *               of k have k numbers between them.
+ *   SK_HOOKED   split {1..2n-1, 2n+1} into n pairs (a_k, a_k + k).
+ *
+ * Method (Sec. 2.1, Lemma 2.1): the number of ordered pairings C(n) is the
+ * coefficient of x_1...x_{2n} in prod_k f_k with f_k = sum_i x_i x_{i+d_k},
+ * equal to 2^{-2n} times the sum over x in {+1,-1}^{2n} of (prod x) prod_k f_k.
+ * The library evaluates the half of the sum with the first sign fixed to +1
+ * (Lemma 2.2), visits sign vectors in Gray-code order on the GPU, takes the
+ * products modulo several primes below 2^46 and recombines them on the host by
+ * the Chinese remainder theorem (Sec. 2.2).
+ *
+ * Conventions for every entry point:
+ *   - All pointers are host pointers unless the name says dev_.
+ *   - The caller owns every buffer it passes; the library keeps no pointer to
+ *     it after the call returns.  Device memory the library needs for one call
+ *     is allocated and freed inside that call.
+ *   - A stream argument is a hipStream_t passed as void*; NULL means the
+ *     library's own stream.  Calls return after their work has completed.
+ *   - Errors are reported only through the status code.  On error, outputs
+ *     are left untouched.  No C++ exception crosses this interface.
+ *   - Calls are thread-safe with respect to each other except where noted.
+ */
+#ifndef SKOLEM_H
+#define SKOLEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { SK_SKOLEM = 0, SK_LANGFORD = 1, SK_HOOKED = 2 } sk_variant;
+
+typedef enum {
+    SK_OK = 0,
+    SK_EINVAL = -1,   /* bad argument: n out of range, unknown variant, bad chunk id, NULL output */
+    SK_ERANGE = -2,   /* the requested primes do not cover the range the result needs */
+    SK_EDEVICE = -3,  /* a HIP runtime error; sk_last_error() has the runtime's message */
+    SK_ECHECK = -4,   /* a self-check failed: the result is not trusted (silent-error guard) */
+    SK_ENOMEM = -5,   /* host or device allocation failed, or a workspace is too small */
+    SK_EABORTED = -6, /* the progress callback asked to stop */
+    SK_ENOLIB = -7    /* the library was built without a kernel for this instance shape */
+} sk_status;
+
+/* Flags for sk_count / sk_instance.flags */
+#define SK_ORDERED     0x1u /* count reflections as distinct (A004075 / A176127 style);
+                               default: reflections counted once for Skolem and Langford,
+                               n > 1 (Sec. 1.3); hooked counts are never halved */
+#define SK_NO_SHORTCUT 0x2u /* evaluate the sum even when the existence conditions
+                               (Sec. 1.1) already give 0 */
+#define SK_VERIFY      0x4u /* run the whole sum a second time modulo a disjoint set of
+                               primes and require both results to agree (the analogue of
+                               the paper's duplicate GPU jobs, Sec. 1.3) */
+
+/* Unsigned 128-bit integer; every count with n <= 32 fits. */
+typedef struct { uint64_t lo, hi; } sk_u128;
+
+/* Launch shape.  Zero in a field means "library default / autotuned".
+ *   log2_chunk_terms : sign vectors evaluated by one wavefront (one chunk)
+ *   waves_per_launch : wavefronts per kernel launch (the host splits the work
+ *                      into launches of this many chunks)
+ *   primes           : primes per pass for sk_count (1..4); default the fewest
+ *                      whose product exceeds n! * 2^8 (n! bounds every count)
+ *   kernel           : kernel body (see sk_kernel_name); 0 = fastest built     */
+typedef struct {
+    int log2_chunk_terms;
+    int waves_per_launch;
+    int primes;
+    int kernel;
+} sk_tuning;
+
+/* Timing and shape of the last completed call on this thread. */
+typedef struct {
+    double kernel_ms;        /* sum of kernel durations (HIP events on the launch stream) */
+    double wall_ms;          /* whole call, host clock */
+    uint64_t terms;          /* sign vectors evaluated (x_1 fixed) */
+    uint64_t launches;       /* kernel launches */
+    uint64_t chunks;         /* wavefront work units */
+    int nprimes;             /* primes used per pass */
+    int passes;              /* 1, or 2 with SK_VERIFY */
+    int log2_chunk_terms;
+    int kernel_variant;      /* which kernel body ran (see sk_kernel_name) */
+    double ms_per_launch_avg;
+    uint64_t primes[8];
+} sk_stats;
+
+/* Progress callback: return nonzero to abort (the call then returns SK_EABORTED). */
+typedef int (*sk_progress_fn)(void *ctx, uint64_t terms_done, uint64_t terms_total);
+
+/* Selects the HIP device used by later calls of this thread (default 0). */
+sk_status sk_set_device(int device);
+
+/*
+ * sk_count -- exact number of pairings for (n, variant), Sec. 2.
+ *   n       : 1..32 (Skolem, Langford), 1..31 (hooked)
+ *   flags   : SK_ORDERED | SK_NO_SHORTCUT | SK_VERIFY
+ *   out     : receives the count
+ * Errors: SK_EINVAL, SK_EDEVICE, SK_ECHECK (CRT result above the a priori bound
+ * n!, or the SK_VERIFY passes disagree), SK_ENOLIB.
+ */
+sk_status sk_count(int n, int variant, unsigned flags, sk_u128 *out);
+
+/* sk_count with a launch shape (NULL: defaults), a stream, a progress
+ * callback (NULL: none) and a statistics record (NULL: not wanted). */
+sk_status sk_count_ex(int n, int variant, unsigned flags, const sk_tuning *tune,
+                      void *stream, sk_progress_fn progress, void *progress_ctx,
+                      sk_stats *stats, sk_u128 *out);
+
+/*
+ * sk_sign_sum_residues -- the half-sum of Lemma 2.1 with x_1 = +1, before the
+ * division by 2^{2n-1}:  H = sum_{x : x_1 = +1} (prod x) prod_k f_k(x),
+ * reduced modulo each given prime.
+ *   primes   : nprimes odd primes with 2^45 < p < 2^46 (caller's choice)
+ *   residues : nprimes outputs, H mod p in [0, p)
+ * Errors: SK_EINVAL (prime out of range), SK_EDEVICE, SK_ENOLIB.
+ */
+sk_status sk_sign_sum_residues(int n, int variant, const uint64_t *primes, int nprimes,
+                               const sk_tuning *tune, void *stream, uint64_t *residues);
+
+/*
+ * sk_partial_chunks -- per-chunk partial sums (Sec. 2.2: the sign space split
+ * into independent parts whose results are added at the end).
+ *
+ * Chunk definition.  Order the 2n sign variables by position.  Variable 1 is
+ * fixed to +1.  The six variables at the highest positions are never fixed by
+ * a chunk.  A chunk of a split into 2^c chunks fixes the c variables directly
+ * below those six: bit b of the chunk id sets x = -1 (bit set) or +1 (clear)
+ * for the variable with 1-based rank (2n - 6 - c + 1 + b) in position order.
+ * A chunk then holds 2^(2n-1-c) sign vectors.
+ *
+ *   log2_chunks : c, 0 <= c <= 2n - 7 - (the count of low variables the
+ *                 kernel walks; sk_max_chunk_bits gives the largest legal c)
+ *   chunk_ids   : nchunks ids, each < 2^c (repeats allowed)
+ *   primes      : nprimes primes with 2^45 < p < 2^46
+ *   residues_out: nchunks x nprimes, row-major, each the chunk's signed sum
+ *                 of (prod x) prod_k f_k(x) modulo the prime, in [0, p)
+ * Errors: SK_EINVAL, SK_EDEVICE, SK_ENOLIB.
+ */
+sk_status sk_partial_chunks(int n, int variant, int log2_chunks, const uint64_t *chunk_ids,
+                            size_t nchunks, const uint64_t *primes, int nprimes, void *stream,
+                            uint64_t *residues_out);
+
+/* Largest legal log2_chunks for sk_partial_chunks (negative on bad input). */
+int sk_max_chunk_bits(int n, int variant);
+
+/* How the library splits the sign variables of (n, variant).  Host only. */
+typedef struct {
+    int m;            /* sign variables, 2n */
+    int n_lane;       /* highest variables enumerated across the 64 lanes */
+    int n_walk;       /* lowest free variables walked in Gray-code order */
+    int n_job;        /* the variables between them (chunk and job bits) */
+    int quads;        /* factor slots / 4 */
+    int groups;       /* exact fp64 product groups per term */
+    int halved;       /* factors with an even number of pairs, stored as f_k / 2 */
+    int primes;       /* primes per pass chosen by sk_count */
+    int slot_factor[32]; /* factor index k-1 in each slot, -1 for a constant-1 slot */
+} sk_plan_desc;
+
+sk_status sk_describe(int n, int variant, sk_plan_desc *out);
+
+/* Describes a status code (static string). */
+const char *sk_strerror(sk_status s);
+
+/* Message of the last HIP error seen by this thread ("" if none). */
+const char *sk_last_error(void);
+
+/* Decimal text of x into buf (NUL-terminated); returns the length, or -1 if
+ * len is too small. */
+int sk_u128_to_decimal(sk_u128 x, char *buf, size_t len);
+
+/* Name of a kernel body, for reports and profiles. */
+const char *sk_kernel_name(int kernel_variant);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKOLEM_H */

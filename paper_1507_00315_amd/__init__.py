@@ -1,0 +1,228 @@
+"""Exact and approximate counting of Skolem, Langford and hooked Skolem pairings
+on AMD Instinct MI355X (gfx950), after arXiv 1507.00315.
+
+Thin ctypes binding over the C ABI in ``include/skolem.h``: argument
+marshalling only.  Every step of the computation runs in ``libskolem.so``
+(host planning and CRT in C++, the sums in HIP kernels).  There is no
+fallback: if the library is missing this module raises on import of the
+binding (``lib()``), and if no GPU is present the calls report a device error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Callable, Dict, Iterable, List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libskolem.so")
+
+SKOLEM, LANGFORD, HOOKED = 0, 1, 2
+VARIANTS = {"skolem": SKOLEM, "langford": LANGFORD, "hooked": HOOKED}
+
+ORDERED, NO_SHORTCUT, VERIFY = 0x1, 0x2, 0x4
+
+STATUS = {0: "SK_OK", -1: "SK_EINVAL", -2: "SK_ERANGE", -3: "SK_EDEVICE", -4: "SK_ECHECK",
+          -5: "SK_ENOMEM", -6: "SK_EABORTED", -7: "SK_ENOLIB"}
+
+
+class SkolemError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str = ""):
+        self.status = status
+        msg = f"{what}: {STATUS.get(status, status)}"
+        if detail:
+            msg += f" ({detail})"
+        super().__init__(msg)
+
+
+class U128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+    def value(self) -> int:
+        return (int(self.hi) << 64) | int(self.lo)
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("log2_chunk_terms", ctypes.c_int), ("waves_per_launch", ctypes.c_int),
+                ("primes", ctypes.c_int), ("kernel", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("kernel_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
+                ("terms", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("chunks", ctypes.c_uint64), ("nprimes", ctypes.c_int), ("passes", ctypes.c_int),
+                ("log2_chunk_terms", ctypes.c_int), ("kernel_variant", ctypes.c_int),
+                ("ms_per_launch_avg", ctypes.c_double), ("primes", ctypes.c_uint64 * 8)]
+
+    def as_dict(self) -> Dict:
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "primes"}
+        d["primes"] = [int(x) for x in self.primes if x]
+        return d
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("n_lane", ctypes.c_int), ("n_walk", ctypes.c_int),
+                ("n_job", ctypes.c_int), ("quads", ctypes.c_int), ("groups", ctypes.c_int),
+                ("halved", ctypes.c_int), ("primes", ctypes.c_int), ("slot_factor", ctypes.c_int * 32)]
+
+
+PROGRESS_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64)
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libskolem.so (built by ``paper_1507_00315_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_1507_00315_amd.build` "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    c_int, c_uint, c_size, vp = ctypes.c_int, ctypes.c_uint, ctypes.c_size_t, ctypes.c_void_p
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    L.sk_set_device.argtypes = [c_int]
+    L.sk_count.argtypes = [c_int, c_int, c_uint, ctypes.POINTER(U128)]
+    L.sk_count_ex.argtypes = [c_int, c_int, c_uint, ctypes.POINTER(Tuning), vp, PROGRESS_FN, vp,
+                              ctypes.POINTER(Stats), ctypes.POINTER(U128)]
+    L.sk_sign_sum_residues.argtypes = [c_int, c_int, u64p, c_int, ctypes.POINTER(Tuning), vp, u64p]
+    L.sk_partial_chunks.argtypes = [c_int, c_int, c_int, u64p, c_size, u64p, c_int, vp, u64p]
+    L.sk_max_chunk_bits.argtypes = [c_int, c_int]
+    L.sk_describe.argtypes = [c_int, c_int, ctypes.POINTER(PlanDesc)]
+    L.sk_strerror.argtypes = [c_int]
+    L.sk_strerror.restype = ctypes.c_char_p
+    L.sk_last_error.restype = ctypes.c_char_p
+    L.sk_kernel_name.argtypes = [c_int]
+    L.sk_kernel_name.restype = ctypes.c_char_p
+    for fn in ("sk_set_device", "sk_count", "sk_count_ex", "sk_sign_sum_residues", "sk_partial_chunks",
+               "sk_max_chunk_bits", "sk_describe"):
+        getattr(L, fn).restype = c_int
+    _lib = L
+    return L
+
+
+EXPORTED = ["sk_set_device", "sk_count", "sk_count_ex", "sk_sign_sum_residues", "sk_partial_chunks",
+            "sk_max_chunk_bits", "sk_describe", "sk_strerror", "sk_last_error", "sk_u128_to_decimal", "sk_kernel_name"]
+
+
+def _variant(v) -> int:
+    if isinstance(v, str):
+        return VARIANTS[v.lower()]
+    return int(v)
+
+
+def _check(status: int, what: str) -> None:
+    if status != 0:
+        detail = lib().sk_last_error().decode(errors="replace")
+        raise SkolemError(status, what, detail)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):  # torch.cuda.Stream
+        return int(stream.cuda_stream)
+    return int(stream)
+
+
+def _tuning(tuning: Optional[Dict]) -> Optional[Tuning]:
+    if not tuning:
+        return None
+    return Tuning(int(tuning.get("log2_chunk_terms", 0)), int(tuning.get("waves_per_launch", 0)),
+                  int(tuning.get("primes", 0)), int(tuning.get("kernel", 0)))
+
+
+def set_device(device: int) -> None:
+    _check(lib().sk_set_device(device), "sk_set_device")
+
+
+@dataclass
+class CountResult:
+    count: int
+    stats: Dict
+
+
+def count_ex(n: int, variant="skolem", ordered: bool = False, verify: bool = False,
+             no_shortcut: bool = False, tuning: Optional[Dict] = None, stream=None,
+             progress: Optional[Callable[[int, int], Optional[bool]]] = None) -> CountResult:
+    """Exact count (reflections counted once unless ``ordered``) with launch statistics."""
+    flags = (ORDERED if ordered else 0) | (VERIFY if verify else 0) | (NO_SHORTCUT if no_shortcut else 0)
+    out = U128()
+    st = Stats()
+    t = _tuning(tuning)
+
+    def _cb(_ctx, done, total):
+        if progress is None:
+            return 0
+        return 1 if progress(int(done), int(total)) else 0
+
+    cb = PROGRESS_FN(_cb)
+    status = lib().sk_count_ex(n, _variant(variant), flags, ctypes.byref(t) if t else None,
+                               _stream_handle(stream), cb, None, ctypes.byref(st), ctypes.byref(out))
+    _check(status, f"sk_count_ex(n={n}, variant={variant})")
+    return CountResult(out.value(), st.as_dict())
+
+
+def count(n: int, variant="skolem", ordered: bool = False, verify: bool = False,
+          no_shortcut: bool = False) -> int:
+    """Exact number of pairings (Sec. 2).  ``ordered`` counts reflections as distinct."""
+    flags = (ORDERED if ordered else 0) | (VERIFY if verify else 0) | (NO_SHORTCUT if no_shortcut else 0)
+    out = U128()
+    _check(lib().sk_count(n, _variant(variant), flags, ctypes.byref(out)), f"sk_count(n={n})")
+    return out.value()
+
+
+def _u64_array(values: Sequence[int]):
+    arr = (ctypes.c_uint64 * len(values))()
+    for i, v in enumerate(values):
+        arr[i] = int(v)
+    return arr
+
+
+def sign_sum_residues(n: int, variant, primes: Sequence[int], tuning: Optional[Dict] = None,
+                      stream=None) -> List[int]:
+    """H mod p for each prime: H = sum over x with x_1 = +1 of (prod x) prod_k f_k(x)."""
+    ps = _u64_array(primes)
+    out = (ctypes.c_uint64 * len(primes))()
+    t = _tuning(tuning)
+    _check(lib().sk_sign_sum_residues(n, _variant(variant), ps, len(primes), ctypes.byref(t) if t else None,
+                                      _stream_handle(stream), out), "sk_sign_sum_residues")
+    return [int(x) for x in out]
+
+
+def partial_chunks(n: int, variant, log2_chunks: int, chunk_ids: Sequence[int], primes: Sequence[int],
+                   stream=None) -> List[List[int]]:
+    """Per-chunk residues (see the chunk definition in include/skolem.h)."""
+    ids = _u64_array(chunk_ids)
+    ps = _u64_array(primes)
+    out = (ctypes.c_uint64 * (len(chunk_ids) * len(primes)))()
+    _check(lib().sk_partial_chunks(n, _variant(variant), log2_chunks, ids, len(chunk_ids), ps, len(primes),
+                                   _stream_handle(stream), out), "sk_partial_chunks")
+    k = len(primes)
+    return [[int(out[c * k + i]) for i in range(k)] for c in range(len(chunk_ids))]
+
+
+def max_chunk_bits(n: int, variant) -> int:
+    return int(lib().sk_max_chunk_bits(n, _variant(variant)))
+
+
+def describe(n: int, variant) -> Dict:
+    """Variable split and product grouping the library uses for (n, variant)."""
+    d = PlanDesc()
+    _check(lib().sk_describe(n, _variant(variant), ctypes.byref(d)), "sk_describe")
+    out = {name: getattr(d, name) for name, _ in d._fields_ if name != "slot_factor"}
+    out["slot_factor"] = [int(x) for x in d.slot_factor[: 4 * d.quads]]
+    return out
+
+
+def kernel_name(kv: int) -> str:
+    return lib().sk_kernel_name(kv).decode()
+
+
+def last_stats_dict(st: Stats) -> Dict:
+    return st.as_dict()
+
+
+__all__ = ["count", "count_ex", "sign_sum_residues", "partial_chunks", "max_chunk_bits", "set_device",
+           "SkolemError", "SKOLEM", "LANGFORD", "HOOKED", "lib", "EXPORTED"]

