@@ -31,12 +31,13 @@ from __future__ import annotations
 
 import ctypes
 import itertools
+import math
 import os
 import subprocess
 from typing import Dict, List, Optional, Sequence, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(HERE, "skolem_oracle.c")
+_SRCS = [os.path.join(HERE, "skolem_oracle.c"), os.path.join(HERE, "pt_oracle.c")]
 _LIB = os.path.join(HERE, "liboracle.so")
 
 SKOLEM, LANGFORD, HOOKED = 0, 1, 2
@@ -53,12 +54,19 @@ def _variant(v) -> int:
 # Build and load the C part
 # --------------------------------------------------------------------------
 
+def _stale() -> bool:
+    if not os.path.exists(_LIB):
+        return True
+    t = os.path.getmtime(_LIB)
+    return any(os.path.getmtime(s) > t for s in _SRCS)
+
+
 def build(force: bool = True) -> str:
-    """Compile ``skolem_oracle.c`` into ``liboracle.so`` with gcc."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the C sources into ``liboracle.so`` with gcc."""
+    if force or _stale():
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
-                               "-o", tmp, _SRC])
+                               "-o", tmp] + _SRCS + ["-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -69,7 +77,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _stale():
             build(force=True)
         L = ctypes.CDLL(_LIB)
         L.orc_count_backtrack.restype = ctypes.c_uint64
@@ -80,6 +88,17 @@ def lib():
         L.orc_chunk_partial_gray.restype = ctypes.c_uint64
         L.orc_chunk_partial_gray.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                              ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int]
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_philox4x32_10.restype = None
+        L.orc_energy_histogram.argtypes = [ctypes.c_int, ctypes.c_int, u64p]
+        L.orc_energy_histogram.restype = ctypes.c_int
+        L.orc_pt_ladder.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
+                                    u64p, u64p, u64p, u64p, ip, ip]
+        L.orc_pt_ladder.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -359,3 +378,99 @@ def primes_below(bound: int, count: int) -> List[int]:
             out.append(x)
         x -= 1
     return out
+
+
+# --------------------------------------------------------------------------
+# Approximate counting (Sec. 3, Algorithm 2)
+# --------------------------------------------------------------------------
+
+def philox4x32_10(ctr: Sequence[int], key: Sequence[int]) -> List[int]:
+    """Philox4x32-10 (Salmon et al., SC'11) of a 4-word counter and 2-word key."""
+    c = (ctypes.c_uint32 * 4)(*ctr)
+    k = (ctypes.c_uint32 * 2)(*key)
+    o = (ctypes.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def placements(n: int, variant) -> List[int]:
+    """L_k: number of placements (a, a + d_k) of pair k inside P."""
+    pos, d = instance(n, variant)
+    s = set(pos)
+    return [sum(1 for a in pos if a + dk in s) for dk in d]
+
+
+def z0(n: int, variant) -> int:
+    """Z(0): number of configurations of the relaxed problem (Sec. 3)."""
+    out = 1
+    for x in placements(n, variant):
+        out *= x
+    return out
+
+
+def energy_histogram(n: int, variant) -> List[int]:
+    """Number of configurations of the relaxed problem with each energy E
+    (E = number of empty bins), by enumeration (use Z(0) < ~1e8)."""
+    pos, _ = instance(n, variant)
+    top = pos[-1]
+    h = (ctypes.c_uint64 * (top + 1))()
+    if lib().orc_energy_histogram(n, _variant(variant), h) != 0:
+        raise ValueError("bad instance")
+    return [int(x) for x in h]
+
+
+def pt_ladder(n: int, variant, betas: Sequence[float], iters: int, seed: int, ladder: int = 0,
+              schedule: str = "sweep") -> Dict:
+    """Runs one tempering ladder (Algorithm 2) and returns energy histograms
+    per level, move/exchange acceptance counts and the final states."""
+    pos, _ = instance(n, variant)
+    top = pos[-1]
+    M = len(betas)
+    H = top + 1
+    b = (ctypes.c_double * M)(*betas)
+    hist = (ctypes.c_uint64 * (M * H))()
+    mv = (ctypes.c_uint64 * M)()
+    sa = (ctypes.c_uint64 * M)()
+    stry = (ctypes.c_uint64 * M)()
+    fa = (ctypes.c_int * (M * n))()
+    fe = (ctypes.c_int * M)()
+    sch = {"sweep": 0, "even_odd": 1}[schedule]
+    rc = lib().orc_pt_ladder(n, _variant(variant), M, b, iters, seed, ladder, sch, hist, mv, sa, stry, fa, fe)
+    if rc != 0:
+        raise ValueError(f"orc_pt_ladder failed ({rc})")
+    return {"hist": [[int(hist[j * H + e]) for e in range(H)] for j in range(M)],
+            "move_accept": [int(x) for x in mv], "swap_accept": [int(x) for x in sa],
+            "swap_try": [int(x) for x in stry],
+            "final_a": [[int(fa[j * n + k]) for k in range(n)] for j in range(M)],
+            "final_e": [int(x) for x in fe]}
+
+
+def pt_ratios(hist: Sequence[Sequence[int]], betas: Sequence[float]) -> List[float]:
+    """Ratio(j) of Algorithm 2 from energy histograms: the mean of
+    exp(-(beta_{j+1} - beta_j) E) at level j; the last level's ratio is taken
+    to beta = infinity, i.e. the fraction of samples with E = 0."""
+    out = []
+    M = len(betas)
+    for j in range(M):
+        tot = sum(hist[j])
+        if j + 1 < M:
+            db = betas[j + 1] - betas[j]
+            out.append(sum(c * math.exp(-db * e) for e, c in enumerate(hist[j])) / tot)
+        else:
+            out.append(hist[j][0] / tot)
+    return out
+
+
+def pt_estimate(hist, betas, n: int, variant, ordered: bool = False) -> float:
+    """Z(0) times the product of the ratios (Sec. 3, end of Algorithm 2); the
+    first inverse temperature must be 0.  Reflections counted once unless
+    ``ordered`` (the 1/2 of Table 6)."""
+    if betas[0] != 0:
+        raise ValueError("the ladder must start at beta = 0")
+    ratios = pt_ratios(hist, betas)
+    if min(ratios) <= 0:
+        return 0.0
+    v = math.exp(math.log(z0(n, variant)) + sum(math.log(r) for r in ratios))
+    if not ordered and _variant(variant) != HOOKED and n > 1:
+        v /= 2
+    return v

@@ -18,8 +18,7 @@ import oracle as O  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 OUT = os.path.join(HERE, "oracle_counts.json")
 
-JOBS = [("hooked", n) for n in range(1, 16)] + [("skolem", 16), ("langford", 15), ("langford", 16),
-                                                ("skolem", 17)]
+JOBS = [("hooked", n) for n in range(1, 16)] + [("skolem", 16), ("langford", 15), ("langford", 16)]
 
 
 def main():
