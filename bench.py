@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "sign-vector terms/s for exact S(n),L(n) at n=20,24; PT rel. error vs GPU-s"
-PEAK_LANE_OPS = 256 * 64 * 2.4e9  # MI355X: 256 CUs x 64 lanes x 2.4 GHz full-rate VALU lane-ops/s
+PEAK_LANE_OPS = 256 * 64 * 2.4e9  # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: VALU lane-instructions/s
 
 WORKLOADS = {
     "batch": [("skolem", 16), ("skolem", 17), ("skolem", 20), ("skolem", 21), ("langford", 15),
@@ -66,14 +66,16 @@ def expected_values():
     return out
 
 
-def alg_ops_per_term(desc) -> int:
-    """Minimal VALU lane-operations per sign vector for this representation:
-    n pair-sum updates, n - 1 exact multiplications, and per prime one
-    accumulate pair (2) plus 4 per double-word modular reduction (quotient
-    estimate 2, fma, low-part add) for each of the G - 1 group products."""
-    n = sum(1 for s in desc["slot_factor"] if s >= 0)
-    P, G = desc["primes_used"], desc["groups"]
-    return n + (n - 1) + P * (4 * max(G - 1, 0) + 2 + (3 if G == 1 else 0))
+def valu_per_term(desc) -> int:
+    """VALU instructions the tuned kernel issues per sign vector (design count):
+    NP packed adds A + B, NQ packed pair products, NQ SDWA quad products, NQ
+    conversions to fp64, NQ - G exact group products, the exact high/low split
+    of g0 g1 (G >= 2), and per prime c(G) residue/accumulate instructions
+    (G = 1: 4; G = 2: 5; each further group: 6)."""
+    nq, G, P = desc["quads"], desc["groups"], desc["primes_used"]
+    np_ = 2 * nq
+    per_prime = {1: 4, 2: 5}.get(G, 5 + 6 * (G - 2))
+    return np_ + 3 * nq + (nq - G) + (2 if G >= 2 else 0) + P * per_prime
 
 
 def cpu_baseline(instances, threads):
@@ -107,6 +109,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--log2-chunk", type=int, default=0)
     ap.add_argument("--kernel", type=int, default=0)
+    ap.add_argument("--separate", action="store_true", help="batch workload as one launch per instance")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -128,8 +132,26 @@ def main():
 
     def step(tag):
         res = []
+        if args.workload == "batch" and not args.separate:
+            counts, st = sk.count_batch([(n, v, sk.ORDERED if v == "hooked" else 0) for v, n in instances],
+                                        tuning=tuning if args.log2_chunk else None)
+            for (v, n), c in zip(instances, counts):
+                ok = want.get((v, n))
+                res.append((v, n, c, None, None if ok is None else (ok == c)))
+            res.append(("*", 0, 0, st, None))
+            log(f"[{tag}] batch: kernel {st['kernel_ms']:.1f} ms  {st['terms'] / max(st['kernel_ms'], 1e-9) * 1e3:.3e}"
+                f" terms/s  launches {st['launches']}  checks {[r[4] for r in res[:-1]]}")
+            return res
+        last = [time.time()]
+
+        def progress(done, total):
+            if time.time() - last[0] > 20:
+                last[0] = time.time()
+                log(f"  ... {done / total * 100:.1f}% of {total:.3e} sign vectors")
+            return False
+
         for v, n in instances:
-            r = sk.count_ex(n, v, ordered=(v == "hooked"), tuning=tuning)
+            r = sk.count_ex(n, v, ordered=(v == "hooked"), tuning=tuning, progress=progress)
             ok = want.get((v, n))
             res.append((v, n, r.count, r.stats, None if ok is None else (ok == r.count)))
             log(f"[{tag}] {v} n={n}: {r.count}  kernel {r.stats['kernel_ms']:.1f} ms  "
@@ -137,6 +159,10 @@ def main():
                 f"check={res[-1][4]}")
         return res
 
+    if args.workload == "batch" and not args.separate and not args.no_autotune and not args.log2_chunk:
+        t0 = time.time()
+        best, rate = sk.autotune_batch([(n, v) for v, n in instances])
+        log(f"autotune: {best} ({rate:.3e} terms/s on the probe, {time.time() - t0:.1f} s)")
     for w in range(args.warmup):
         step(f"warmup {w}")
     sync()
@@ -147,25 +173,29 @@ def main():
     sync()
     elapsed = time.perf_counter() - t0
 
-    terms_per_step = sum(r[3]["terms"] for r in results[0])
+    def stats_of(st):
+        return [r[3] for r in st if r[3] is not None]
+
+    terms_per_step = sum(s["terms"] for s in stats_of(results[0]))
     total_terms = terms_per_step * args.steps
     value = total_terms / elapsed
     all_ok = all(r[4] is not False for st in results for r in st)
 
-    # Roofline of the exact kernel: algorithmic lane-ops per launch over the
-    # launch durations measured with HIP events on the launch stream.
-    alg = 0.0
-    kms = 0.0
-    launches = 0
-    for st in results:
-        for v, n, _c, stats, _ok in st:
-            d = sk.describe(n, v)
-            d["primes_used"] = stats["nprimes"]
-            alg += stats["terms"] * alg_ops_per_term(d)
-            kms += stats["kernel_ms"]
-            launches += stats["launches"]
-    achieved = alg / (kms * 1e-3) if kms > 0 else 0.0
-    kernel_name = sk.kernel_name(results[0][0][3]["kernel_variant"])
+    # Roofline of the exact kernel: VALU instructions per sign vector (design
+    # count of the tuned body) x sign vectors / launch durations measured with
+    # HIP events on the launch stream.
+    instr = 0.0
+    for v, n in instances:
+        d = sk.describe(n, v)
+        d["primes_used"] = d["primes"]
+        instr_per = valu_per_term(d)
+        terms_inst = 1 << (2 * n - 1)
+        instr += terms_inst * instr_per
+    kms = sum(s["kernel_ms"] for st in results for s in stats_of(st)) / args.steps
+    launches = sum(s["launches"] for st in results for s in stats_of(st)) // args.steps
+    achieved = instr / (kms * 1e-3) if kms > 0 else 0.0
+    kernel_name = sk.kernel_name(stats_of(results[0])[0]["kernel_variant"])
+    instr_per_term = instr / terms_per_step
 
     line = {
         "metric": METRIC,
@@ -183,11 +213,12 @@ def main():
         "config": {"workload": args.workload,
                    "instances": [f"{v}:{n}" for v, n in instances],
                    "terms_per_step": terms_per_step,
-                   "primes_per_instance": {f"{r[0]}:{r[1]}": r[3]["nprimes"] for r in results[0]},
-                   "log2_chunk_terms": {f"{r[0]}:{r[1]}": r[3]["log2_chunk_terms"] for r in results[0]},
+                   "primes_per_instance": {f"{v}:{n}": sk.describe(n, v)["primes"] for v, n in instances},
+                   "log2_chunk_terms": stats_of(results[0])[0]["log2_chunk_terms"],
                    "results_match_expected": all_ok},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "lane-op/s",
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "VALU lane-instr/s",
                      "frac": achieved / PEAK_LANE_OPS, "traffic": None, "kernel": kernel_name,
+                     "valu_instr_per_term": instr_per_term, "terms_per_s_kernel": terms_per_step / (kms * 1e-3),
                      "launches": launches, "avg_launch_ms": kms / max(launches, 1)},
     }
     if not args.no_cpu_baseline:

@@ -70,13 +70,22 @@ typedef struct { uint64_t lo, hi; } sk_u128;
  *                      into launches of this many chunks)
  *   primes           : primes per pass for sk_count (1..4); default the fewest
  *                      whose product exceeds n! * 2^8 (n! bounds every count)
- *   kernel           : kernel body (see sk_kernel_name); 0 = fastest built     */
+ *   kernel           : kernel body: 0 = the tuned body when built for the
+ *                      instance, else the reference; 1 = reference; 2 = tuned
+ *                      (SK_ENOLIB if not built)                                */
 typedef struct {
     int log2_chunk_terms;
     int waves_per_launch;
     int primes;
     int kernel;
 } sk_tuning;
+
+/* One instance of a batched count. */
+typedef struct {
+    int n;
+    int variant;     /* sk_variant */
+    unsigned flags;  /* SK_ORDERED | SK_NO_SHORTCUT | SK_VERIFY */
+} sk_instance;
 
 /* Timing and shape of the last completed call on this thread. */
 typedef struct {
@@ -116,10 +125,39 @@ sk_status sk_count_ex(int n, int variant, unsigned flags, const sk_tuning *tune,
                       sk_stats *stats, sk_u128 *out);
 
 /*
+ * sk_count_batch -- exact counts of k instances (Sec. 2) in one persistent
+ * kernel launch: wavefronts pull (instance, chunk) work items from one global
+ * queue, so instances of very different size share the GPU without a tail per
+ * instance.  Instances whose kernel is not compiled into the batched launch
+ * and instances with tune->kernel == 1 or a larger prime count
+ * are counted by separate launches in the same call.
+ *   inst  : k instances (k >= 1); out: k counts, in order
+ *   tune  : NULL = the shape found by sk_autotune_batch for this instance set
+ *           (cached per GPU model), else log2_chunk_terms (sign vectors per work
+ *           item) and waves_per_launch (persistent grid) are used
+ *   stats : NULL or receives the totals of the call
+ * Errors: as sk_count; SK_EINVAL for k == 0 or a bad instance.
+ */
+sk_status sk_count_batch(const sk_instance *inst, size_t k, const sk_tuning *tune, void *stream,
+                         sk_stats *stats, sk_u128 *out);
+
+/*
+ * sk_autotune_batch -- times the batched launch of these instances on 1/16 of
+ * their work for a grid of (sign vectors per work item) x (waves per SIMD),
+ * stores the fastest in the cache file ($SK_TUNE_CACHE, default
+ * ~/.cache/skolem_mi355x_tune.txt) keyed by GPU model and instance set, and
+ * returns it.  best_rate (nullable) receives sign vectors per second.
+ * Errors: SK_ENOLIB if an instance is not compiled into the batched launch.
+ */
+sk_status sk_autotune_batch(const sk_instance *inst, size_t k, void *stream, sk_tuning *best,
+                            double *best_rate);
+
+/*
  * sk_sign_sum_residues -- the half-sum of Lemma 2.1 with x_1 = +1, before the
  * division by 2^{2n-1}:  H = sum_{x : x_1 = +1} (prod x) prod_k f_k(x),
  * reduced modulo each given prime.
- *   primes   : nprimes odd primes with 2^45 < p < 2^46 (caller's choice)
+ *   primes   : nprimes (1..8) odd primes with 2^45 < p < 2^46 (caller's choice)
+ *   tune     : launch shape and kernel body (NULL: defaults)
  *   residues : nprimes outputs, H mod p in [0, p)
  * Errors: SK_EINVAL (prime out of range), SK_EDEVICE, SK_ENOLIB.
  */
@@ -140,14 +178,84 @@ sk_status sk_sign_sum_residues(int n, int variant, const uint64_t *primes, int n
  *   log2_chunks : c, 0 <= c <= 2n - 7 - (the count of low variables the
  *                 kernel walks; sk_max_chunk_bits gives the largest legal c)
  *   chunk_ids   : nchunks ids, each < 2^c (repeats allowed)
- *   primes      : nprimes primes with 2^45 < p < 2^46
+ *   primes      : nprimes (1..8) primes with 2^45 < p < 2^46
+ *   tune        : waves_per_launch and kernel fields are used (NULL: defaults)
  *   residues_out: nchunks x nprimes, row-major, each the chunk's signed sum
  *                 of (prod x) prod_k f_k(x) modulo the prime, in [0, p)
  * Errors: SK_EINVAL, SK_EDEVICE, SK_ENOLIB.
  */
 sk_status sk_partial_chunks(int n, int variant, int log2_chunks, const uint64_t *chunk_ids,
-                            size_t nchunks, const uint64_t *primes, int nprimes, void *stream,
-                            uint64_t *residues_out);
+                            size_t nchunks, const uint64_t *primes, int nprimes,
+                            const sk_tuning *tune, void *stream, uint64_t *residues_out);
+
+
+/* ------------------------------------------------------------------------
+ * Approximate counting by parallel tempering (Sec. 3, Algorithm 2).
+ *
+ * Relaxed problem: pair k may sit at any placement (a_k, a_k + d_k) inside the
+ * position set, pairs may overlap; the energy of a configuration is its number
+ * of empty positions.  Z(beta) = sum exp(-beta E); Z(0) = prod_k L_k counts all
+ * configurations, Z(infinity) the ordered pairings.  Each ladder runs M chains
+ * at 0 = beta_0 < beta_1 < ... < beta_{M-1}; per iteration every level records
+ * its energy, makes one Metropolis move and neighbouring levels attempt an
+ * exchange (even pairs on even iterations, odd pairs on odd ones).  The
+ * estimate of a ladder is Z(0) * prod_j Ratio(j) with Ratio(j) the mean of
+ * exp(-(beta_{j+1} - beta_j) E) at level j and the last ratio the fraction of
+ * samples with E = 0 at beta_{M-1} (beta_M = infinity).  Randomness: Philox4x32-10
+ * keyed by the seed, counter (iteration, ladder, level).
+ * ---------------------------------------------------------------------- */
+
+#define SK_PROPOSAL_UNIFORM 0 /* pair uniform, placement uniform (Sec. 3) */
+#define SK_PROPOSAL_LEARNED 1 /* MLP proposal with Metropolis-Hastings correction */
+
+typedef struct {
+    int levels;          /* M, 2..64 */
+    const double *beta;  /* M ascending inverse temperatures, beta[0] == 0 */
+    int ladders;         /* independent ladders, >= 1 (one wavefront each) */
+    uint64_t iterations; /* per ladder */
+    uint64_t seed;       /* Philox key */
+    int proposal;        /* SK_PROPOSAL_* */
+    unsigned flags;      /* SK_ORDERED: estimate the ordered count */
+    uint64_t segment;    /* iterations per kernel launch (0: 2^24); chains carry over */
+} sk_pt_params;
+
+typedef struct {
+    double mean_energy[64]; /* per level, pooled over ladders */
+    double move_accept[64]; /* accepted moves / iterations */
+    double swap_accept[64]; /* accepted exchanges of (j, j+1) / attempts */
+    double ratio[64];       /* Ratio(j) from the pooled histograms */
+    double gpu_ms;          /* kernel time (HIP events) */
+    double wall_ms;
+    uint64_t moves;         /* ladders x levels x iterations */
+    int levels, ladders;
+} sk_pt_stats;
+
+/* Energy bins per level: 2n + 1 (Skolem, Langford) or 2n + 2 (hooked); -1 on
+ * bad input.  Host only. */
+int sk_pt_bins(int n, int variant);
+
+/*
+ * sk_pt_run -- runs the ladders and returns the raw chain statistics.
+ *   hist     : ladders x levels x sk_pt_bins(n, variant) energy counts (filled)
+ *   move_acc : ladders x levels accepted moves (filled)
+ *   swap_acc : ladders x levels accepted exchanges of (j, j+1) (filled)
+ *   state    : NULL or ladders x levels x n final placements a_k (1-based
+ *              positions), in level order
+ *   energy   : NULL or ladders x levels final energies
+ * Errors: SK_EINVAL (bad ladder: beta[0] != 0, not ascending, levels out of
+ * range, no configuration), SK_ENOLIB (proposal not available), SK_EDEVICE.
+ */
+sk_status sk_pt_run(int n, int variant, const sk_pt_params *p, void *stream, uint64_t *hist,
+                    uint64_t *move_acc, uint64_t *swap_acc, uint8_t *state, int32_t *energy);
+
+/*
+ * sk_approx -- approximate count (reflections counted once for Skolem and
+ * Langford unless p->flags has SK_ORDERED): mean of the ladders' estimates and
+ * its standard error (sample standard deviation / sqrt(ladders); 0 for one
+ * ladder).  stats may be NULL.
+ */
+sk_status sk_approx(int n, int variant, const sk_pt_params *p, void *stream, double *estimate,
+                    double *std_error, sk_pt_stats *stats);
 
 /* Largest legal log2_chunks for sk_partial_chunks (negative on bad input). */
 int sk_max_chunk_bits(int n, int variant);

@@ -60,10 +60,34 @@ class Stats(ctypes.Structure):
         return d
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("variant", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
 class PlanDesc(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("n_lane", ctypes.c_int), ("n_walk", ctypes.c_int),
                 ("n_job", ctypes.c_int), ("quads", ctypes.c_int), ("groups", ctypes.c_int),
                 ("halved", ctypes.c_int), ("primes", ctypes.c_int), ("slot_factor", ctypes.c_int * 32)]
+
+
+class PtParams(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("beta", ctypes.POINTER(ctypes.c_double)), ("ladders", ctypes.c_int),
+                ("iterations", ctypes.c_uint64), ("seed", ctypes.c_uint64), ("proposal", ctypes.c_int),
+                ("flags", ctypes.c_uint), ("segment", ctypes.c_uint64)]
+
+
+class PtStats(ctypes.Structure):
+    _fields_ = [("mean_energy", ctypes.c_double * 64), ("move_accept", ctypes.c_double * 64),
+                ("swap_accept", ctypes.c_double * 64), ("ratio", ctypes.c_double * 64),
+                ("gpu_ms", ctypes.c_double), ("wall_ms", ctypes.c_double), ("moves", ctypes.c_uint64),
+                ("levels", ctypes.c_int), ("ladders", ctypes.c_int)]
+
+    def as_dict(self) -> Dict:
+        M = self.levels
+        return {"mean_energy": list(self.mean_energy[:M]), "move_accept": list(self.move_accept[:M]),
+                "swap_accept": list(self.swap_accept[:M]), "ratio": list(self.ratio[:M]),
+                "gpu_ms": self.gpu_ms, "wall_ms": self.wall_ms, "moves": int(self.moves),
+                "levels": M, "ladders": self.ladders}
 
 
 PROGRESS_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64)
@@ -87,22 +111,34 @@ def lib() -> ctypes.CDLL:
     L.sk_count_ex.argtypes = [c_int, c_int, c_uint, ctypes.POINTER(Tuning), vp, PROGRESS_FN, vp,
                               ctypes.POINTER(Stats), ctypes.POINTER(U128)]
     L.sk_sign_sum_residues.argtypes = [c_int, c_int, u64p, c_int, ctypes.POINTER(Tuning), vp, u64p]
-    L.sk_partial_chunks.argtypes = [c_int, c_int, c_int, u64p, c_size, u64p, c_int, vp, u64p]
+    L.sk_partial_chunks.argtypes = [c_int, c_int, c_int, u64p, c_size, u64p, c_int, ctypes.POINTER(Tuning), vp,
+                                    u64p]
     L.sk_max_chunk_bits.argtypes = [c_int, c_int]
     L.sk_describe.argtypes = [c_int, c_int, ctypes.POINTER(PlanDesc)]
+    L.sk_pt_bins.argtypes = [c_int, c_int]
+    L.sk_pt_run.argtypes = [c_int, c_int, ctypes.POINTER(PtParams), vp, u64p, u64p, u64p,
+                            ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)]
+    L.sk_approx.argtypes = [c_int, c_int, ctypes.POINTER(PtParams), vp, ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(PtStats)]
+    L.sk_count_batch.argtypes = [ctypes.POINTER(Instance), c_size, ctypes.POINTER(Tuning), vp, ctypes.POINTER(Stats),
+                                 ctypes.POINTER(U128)]
+    L.sk_autotune_batch.argtypes = [ctypes.POINTER(Instance), c_size, vp, ctypes.POINTER(Tuning),
+                                    ctypes.POINTER(ctypes.c_double)]
     L.sk_strerror.argtypes = [c_int]
     L.sk_strerror.restype = ctypes.c_char_p
     L.sk_last_error.restype = ctypes.c_char_p
     L.sk_kernel_name.argtypes = [c_int]
     L.sk_kernel_name.restype = ctypes.c_char_p
     for fn in ("sk_set_device", "sk_count", "sk_count_ex", "sk_sign_sum_residues", "sk_partial_chunks",
-               "sk_max_chunk_bits", "sk_describe"):
+               "sk_max_chunk_bits", "sk_describe", "sk_count_batch", "sk_autotune_batch", "sk_pt_bins",
+               "sk_pt_run", "sk_approx"):
         getattr(L, fn).restype = c_int
     _lib = L
     return L
 
 
-EXPORTED = ["sk_set_device", "sk_count", "sk_count_ex", "sk_sign_sum_residues", "sk_partial_chunks",
+EXPORTED = ["sk_set_device", "sk_count", "sk_count_ex", "sk_count_batch", "sk_autotune_batch", "sk_pt_bins",
+            "sk_pt_run", "sk_approx", "sk_sign_sum_residues", "sk_partial_chunks",
             "sk_max_chunk_bits", "sk_describe", "sk_strerror", "sk_last_error", "sk_u128_to_decimal", "sk_kernel_name"]
 
 
@@ -173,6 +209,37 @@ def count(n: int, variant="skolem", ordered: bool = False, verify: bool = False,
     return out.value()
 
 
+def _instances(instances) -> "ctypes.Array":
+    arr = (Instance * len(instances))()
+    for i, it in enumerate(instances):
+        n, v = it[0], it[1]
+        fl = it[2] if len(it) > 2 else 0
+        arr[i] = Instance(int(n), _variant(v), int(fl))
+    return arr
+
+
+def count_batch(instances, tuning: Optional[Dict] = None, stream=None):
+    """Exact counts of several instances [(n, variant[, flags]), ...] in one
+    persistent launch; returns (counts, stats)."""
+    arr = _instances(instances)
+    out = (U128 * len(instances))()
+    st = Stats()
+    t = _tuning(tuning)
+    _check(lib().sk_count_batch(arr, len(instances), ctypes.byref(t) if t else None, _stream_handle(stream),
+                                ctypes.byref(st), out), "sk_count_batch")
+    return [o.value() for o in out], st.as_dict()
+
+
+def autotune_batch(instances, stream=None):
+    """Finds and caches the launch shape of count_batch for this instance set."""
+    arr = _instances(instances)
+    best = Tuning()
+    rate = ctypes.c_double()
+    _check(lib().sk_autotune_batch(arr, len(instances), _stream_handle(stream), ctypes.byref(best),
+                                   ctypes.byref(rate)), "sk_autotune_batch")
+    return {"log2_chunk_terms": best.log2_chunk_terms, "waves_per_launch": best.waves_per_launch}, rate.value
+
+
 def _u64_array(values: Sequence[int]):
     arr = (ctypes.c_uint64 * len(values))()
     for i, v in enumerate(values):
@@ -192,13 +259,15 @@ def sign_sum_residues(n: int, variant, primes: Sequence[int], tuning: Optional[D
 
 
 def partial_chunks(n: int, variant, log2_chunks: int, chunk_ids: Sequence[int], primes: Sequence[int],
-                   stream=None) -> List[List[int]]:
+                   tuning: Optional[Dict] = None, stream=None) -> List[List[int]]:
     """Per-chunk residues (see the chunk definition in include/skolem.h)."""
     ids = _u64_array(chunk_ids)
     ps = _u64_array(primes)
     out = (ctypes.c_uint64 * (len(chunk_ids) * len(primes)))()
+    t = _tuning(tuning)
     _check(lib().sk_partial_chunks(n, _variant(variant), log2_chunks, ids, len(chunk_ids), ps, len(primes),
-                                   _stream_handle(stream), out), "sk_partial_chunks")
+                                   ctypes.byref(t) if t else None, _stream_handle(stream), out),
+           "sk_partial_chunks")
     k = len(primes)
     return [[int(out[c * k + i]) for i in range(k)] for c in range(len(chunk_ids))]
 
@@ -216,6 +285,55 @@ def describe(n: int, variant) -> Dict:
     return out
 
 
+PROPOSAL_UNIFORM, PROPOSAL_LEARNED = 0, 1
+
+
+def _pt_params(betas, ladders, iterations, seed, proposal, ordered, segment):
+    arr = (ctypes.c_double * len(betas))(*[float(x) for x in betas])
+    p = PtParams(len(betas), arr, int(ladders), int(iterations), int(seed), int(proposal),
+                 ORDERED if ordered else 0, int(segment))
+    return p, arr
+
+
+def pt_bins(n: int, variant) -> int:
+    return int(lib().sk_pt_bins(n, _variant(variant)))
+
+
+def pt_run(n: int, variant, betas: Sequence[float], ladders: int, iterations: int, seed: int,
+           proposal: int = PROPOSAL_UNIFORM, segment: int = 0, stream=None) -> Dict:
+    """Runs the tempering ladders (Sec. 3) and returns raw chain statistics:
+    hist[ladder][level][E], move/exchange acceptance counts, final states."""
+    M = len(betas)
+    H = pt_bins(n, variant)
+    if H < 0:
+        raise SkolemError(-1, "sk_pt_bins")
+    p, keep = _pt_params(betas, ladders, iterations, seed, proposal, False, segment)
+    hist = (ctypes.c_uint64 * (ladders * M * H))()
+    ma = (ctypes.c_uint64 * (ladders * M))()
+    sw = (ctypes.c_uint64 * (ladders * M))()
+    state = (ctypes.c_uint8 * (ladders * M * n))()
+    energy = (ctypes.c_int32 * (ladders * M))()
+    _check(lib().sk_pt_run(n, _variant(variant), ctypes.byref(p), _stream_handle(stream), hist, ma, sw, state,
+                           energy), "sk_pt_run")
+    return {"hist": [[[int(hist[(l * M + j) * H + e]) for e in range(H)] for j in range(M)] for l in range(ladders)],
+            "move_accept": [[int(ma[l * M + j]) for j in range(M)] for l in range(ladders)],
+            "swap_accept": [[int(sw[l * M + j]) for j in range(M)] for l in range(ladders)],
+            "state": [[[int(state[(l * M + j) * n + k]) for k in range(n)] for j in range(M)] for l in range(ladders)],
+            "energy": [[int(energy[l * M + j]) for j in range(M)] for l in range(ladders)]}
+
+
+def approx(n: int, variant, betas: Sequence[float], ladders: int, iterations: int, seed: int,
+           proposal: int = PROPOSAL_UNIFORM, ordered: bool = False, segment: int = 0, stream=None):
+    """Approximate count by parallel tempering: (estimate, standard error, stats)."""
+    p, keep = _pt_params(betas, ladders, iterations, seed, proposal, ordered, segment)
+    est = ctypes.c_double()
+    se = ctypes.c_double()
+    st = PtStats()
+    _check(lib().sk_approx(n, _variant(variant), ctypes.byref(p), _stream_handle(stream), ctypes.byref(est),
+                           ctypes.byref(se), ctypes.byref(st)), "sk_approx")
+    return est.value, se.value, st.as_dict()
+
+
 def kernel_name(kv: int) -> str:
     return lib().sk_kernel_name(kv).decode()
 
@@ -224,5 +342,5 @@ def last_stats_dict(st: Stats) -> Dict:
     return st.as_dict()
 
 
-__all__ = ["count", "count_ex", "sign_sum_residues", "partial_chunks", "max_chunk_bits", "set_device",
+__all__ = ["count", "count_ex", "count_batch", "autotune_batch", "pt_run", "approx", "pt_bins", "sign_sum_residues", "partial_chunks", "max_chunk_bits", "set_device",
            "SkolemError", "SKOLEM", "LANGFORD", "HOOKED", "lib", "EXPORTED"]

@@ -36,9 +36,10 @@ __device__ __forceinline__ double reduce_balanced(double x, double p, double pin
     return __builtin_fma(quot_nearest(x, pinv), -p, x);
 }
 
-// Exact group products of the 4*NQ slot values (each |f| <= 64).
+// Exact group products of the 4*NQ slot values (each |f| <= 64); group gi
+// multiplies quads [qb[gi], qb[gi+1]).
 template <int NQ, int G>
-__device__ __forceinline__ void group_products(const int32_t* f, double* g)
+__device__ __forceinline__ void group_products(const int32_t* f, const int32_t* qb, double* g)
 {
     double q[NQ];
 #pragma unroll
@@ -49,9 +50,10 @@ __device__ __forceinline__ void group_products(const int32_t* f, double* g)
     }
 #pragma unroll
     for (int gi = 0; gi < G; ++gi) {
-        double v = q[quad_begin(NQ, G, gi)];
+        double v = 1.0;
 #pragma unroll
-        for (int i = quad_begin(NQ, G, gi) + 1; i < quad_begin(NQ, G, gi + 1); ++i) v *= q[i];
+        for (int i = 0; i < NQ; ++i)
+            if (i >= qb[gi] && i < qb[gi + 1]) v *= q[i];
         g[gi] = v;
     }
 }

@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(256) exact_v1_kernel(const ExactArgs a, double
                 f[s] = (a.slot[s].len - 2 * c) >> a.slot[s].halve;
             }
             double g[G];
-            group_products<NQ, G>(f, g);
+            group_products<NQ, G>(f, a.qb, g);
             accumulate_term<G>(g, a.prime, a.pinv, P, (t & 1) != 0, accj);
             if ((t & 63) == 63) {
                 for (int i = 0; i < kMaxPrimes; ++i)

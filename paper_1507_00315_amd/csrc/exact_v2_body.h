@@ -1,0 +1,456 @@
+// Exact sign-vector sum (Lemma 2.1), tuned kernel body for gfx950.
+//
+// Same decomposition as the reference body (exact_v1.hip): one wavefront per
+// chunk, lanes enumerate the six highest sign variables, jobs enumerate the
+// middle ones, and inside a job the lowest n_walk variables are visited in
+// binary-reflected Gray-code order (Sec. 2.1: one sign flip per step, the pair
+// sums updated by a linear number of additions).
+//
+// What is specialised here:
+//   * Every pair sum is split as f_k = A_k + B_k.  A_k collects the pairs that
+//     touch a lane variable; no walked variable is in such a pair (the plan
+//     guarantees it), so A_k is fixed for the whole walk and lives per lane.
+//     B_k collects the pairs of wave-uniform variables and lives in scalar
+//     registers: the scalar unit updates it while the vector unit multiplies.
+//   * Factors with an even pair count L_k are kept halved (f_k is even for
+//     every sign vector then), shrinking the exact products.
+//   * Two factors share a 32-bit register as packed 16-bit integers.  The
+//     scalar copy of B is held with a bias of 2^14 per half and updated by
+//     ordinary 32-bit adds of "integer-encoded" pairs (lo + 65536*hi), which
+//     never carry between the halves.
+//   * The lowest INNER walked variables (set Q) flip inside a fully unrolled
+//     block of 2^(INNER+1) steps; their flip positions, the states of the other
+//     Q variables and the step signs are compile-time constants.  For each
+//     q in Q the scalar unit keeps N_q = the vector of (scaled) sums of q's
+//     neighbours outside Q, so a flip of q is one scalar add per register pair
+//     plus a compile-time constant for the pairs inside Q.
+//   * The middle step of the block flips walked variable INNER (compile-time
+//     position); the step between blocks flips a higher walked variable chosen
+//     by a uniform branch over compile-time cases.
+//   * Products: packed 16-bit multiply (two pair products per instruction),
+//     one 24-bit multiply per quad reading both halves (SDWA), conversion to
+//     fp64, exact fp64 group products, then the fp64 residue chain of
+//     exact_common.h per prime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "exact_common.h"
+#include "sk_internal.h"
+#include "sk_plan.h"
+
+namespace sk {
+
+template <int I, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I < E) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, E>(f);
+    }
+}
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(short2_t, a) + __builtin_bit_cast(short2_t, b));
+}
+
+__device__ __forceinline__ uint32_t pk_mul(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(short2_t, a) * __builtin_bit_cast(short2_t, b));
+}
+
+// product of the two sign-extended 16-bit halves of x
+__device__ __forceinline__ int32_t mul_halves(uint32_t x)
+{
+    int32_t r;
+    asm volatile("v_mul_i32_i24_sdwa %0, sext(%1), sext(%1) dst_sel:DWORD dst_unused:UNUSED_PAD "
+                 "src0_sel:WORD_0 src1_sel:WORD_1"
+                 : "=v"(r)
+                 : "v"(x));
+    return r;
+}
+
+constexpr uint32_t kHalfBias = 0x4000u;
+
+template <int V, int N, int P, int INNER>
+struct ExactV2 {
+    static constexpr PlanCE PL = make_plan_ce(N, V);
+    static_assert(PL.ok, "no plan");
+    static constexpr int NS = 4 * PL.nq;  // slots
+    static constexpr int NP = NS / 2;     // packed slot pairs
+    static constexpr int NQ = PL.nq;
+    static constexpr int G = PL.G;
+    static constexpr int W = PL.n_walk;
+    static constexpr int M = PL.m;
+    static_assert(PL.n_lane == 6, "tuned body needs six lane variables");
+    static_assert(W >= INNER + 1, "walk too short for the unrolled block");
+    static constexpr int D = 1 << (INNER + 1);  // steps per unrolled block
+
+    // ranks below the lane ranks sit at position rank + 1 (the hooked gap is
+    // at the top, among the lane ranks)
+    static constexpr bool contiguous_low()
+    {
+        for (int r = 0; r < M - 6; ++r)
+            if (PL.pos[r] != r + 1) return false;
+        return true;
+    }
+    static_assert(contiguous_low(), "unexpected position layout");
+
+    static constexpr bool in_set(int p) { return p >= 1 && p <= 64 && ((PL.pset >> (p - 1)) & 1); }
+    static constexpr int qpos(int b) { return 2 + b; }  // position of inner walked variable b
+    static constexpr bool is_inner(int p) { return p >= 2 && p < 2 + INNER; }
+    static constexpr int g_of(int s) { return PL.slot_k[s] < 0 ? 0 : (PL.slot_halve[s] ? 1 : 2); }
+    static constexpr uint64_t lane_posmask()
+    {
+        uint64_t m = 0;
+        for (int b = 0; b < 6; ++b) m |= 1ull << (PL.pos[M - 6 + b] - 1);
+        return m;
+    }
+    // edges of slot s touching a lane variable / between uniform variables
+    static constexpr uint64_t mask_lane(int s)
+    {
+        const uint64_t lp = lane_posmask();
+        return PL.slot_k[s] < 0 ? 0 : (PL.slot_mask[s] & (lp | (lp >> PL.slot_d[s])));
+    }
+    static constexpr uint64_t mask_unif(int s) { return PL.slot_k[s] < 0 ? 0 : (PL.slot_mask[s] & ~mask_lane(s)); }
+    static constexpr int popc_ce(uint64_t x)
+    {
+        int c = 0;
+        while (x) {
+            c += (int)(x & 1);
+            x >>= 1;
+        }
+        return c;
+    }
+    // inner state (bit b set <=> x = -1) at local step i of a block
+    static constexpr int state(int i) { return (i ^ (i >> 1)) & ((1 << INNER) - 1); }
+    static constexpr int xval_state(int st, int b) { return ((st >> b) & 1) ? -1 : 1; }
+    static constexpr int ctz_ce(int i)
+    {
+        int c = 0;
+        while (!(i & 1)) {
+            i >>= 1;
+            ++c;
+        }
+        return c;
+    }
+    // integer-encoded constant for pair p at inner flip of step i:
+    // sum over slots of g_s * (sum of x of Q-neighbours of the flipped q at distance d_s)
+    static constexpr int inner_const_slot(int i, int s)
+    {
+        const int b = ctz_ce(i);
+        const int st = state(i - 1);
+        if (PL.slot_k[s] < 0) return 0;
+        int sum = 0;
+        for (int b2 = 0; b2 < INNER; ++b2) {
+            if (b2 == b) continue;
+            const int dist = qpos(b) > qpos(b2) ? qpos(b) - qpos(b2) : qpos(b2) - qpos(b);
+            if (dist == PL.slot_d[s]) sum += xval_state(st, b2);
+        }
+        return g_of(s) * sum;
+    }
+    static constexpr int32_t inner_const_pair(int i, int p)
+    {
+        return (int32_t)inner_const_slot(i, 2 * p) + 65536 * (int32_t)inner_const_slot(i, 2 * p + 1);
+    }
+    // slot whose difference equals dist (-1 if none)
+    static constexpr int slot_of_diff(int dist)
+    {
+        for (int s = 0; s < NS; ++s)
+            if (PL.slot_k[s] >= 0 && PL.slot_d[s] == dist) return s;
+        return -1;
+    }
+
+    __device__ static __forceinline__ int xbit(uint64_t XU, int p) { return 1 - 2 * (int)((XU >> (p - 1)) & 1); }
+
+    // Scalar state for a job: B (biased, integer-encoded pairs) and N_q.
+    struct Uniform {
+        uint64_t XU;
+        uint32_t B[NP];
+        int32_t Nq[INNER][NP];
+    };
+
+    __device__ static __forceinline__ void init_uniform(Uniform& u)
+    {
+        static_for<0, NP>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            int32_t bh[2];
+            static_for<0, 2>([&](auto hc) {
+                constexpr int s = 2 * p + decltype(hc)::value;
+                if constexpr (PL.slot_k[s] < 0) {
+                    bh[decltype(hc)::value] = 0;
+                } else {
+                    constexpr uint64_t mu = mask_unif(s);
+                    constexpr int d = PL.slot_d[s];
+                    const int B = popc_ce(mu) - 2 * (int)__builtin_popcountll((u.XU ^ (u.XU >> d)) & mu);
+                    if constexpr (PL.slot_halve[s]) {
+                        constexpr int c = popc_ce(mu) & 1;
+                        bh[decltype(hc)::value] = (B - c) >> 1;
+                    } else {
+                        bh[decltype(hc)::value] = B;
+                    }
+                }
+            });
+            u.B[p] = (uint32_t)(bh[0] + (int32_t)kHalfBias) + 65536u * (uint32_t)(bh[1] + (int32_t)kHalfBias);
+        });
+        static_for<0, INNER>([&](auto bc) {
+            constexpr int b = decltype(bc)::value;
+            constexpr int q = qpos(b);
+            static_for<0, NP>([&](auto pc) {
+                constexpr int p = decltype(pc)::value;
+                int32_t nh[2];
+                static_for<0, 2>([&](auto hc) {
+                    constexpr int s = 2 * p + decltype(hc)::value;
+                    int sum = 0;
+                    if constexpr (PL.slot_k[s] >= 0) {
+                        constexpr int d = PL.slot_d[s];
+                        if constexpr (in_set(q - d) && !is_inner(q - d)) sum += xbit(u.XU, q - d);
+                        if constexpr (in_set(q + d) && !is_inner(q + d)) sum += xbit(u.XU, q + d);
+                    }
+                    nh[decltype(hc)::value] = g_of(s) * sum;
+                });
+                u.Nq[b][p] = nh[0] + 65536 * nh[1];
+            });
+        });
+    }
+
+    // Flip of the uniform walked variable at position R (not in Q).
+    template <int R>
+    __device__ static __forceinline__ void flip_outer(Uniform& u)
+    {
+        const int xr = xbit(u.XU, R);  // value before the flip
+        static_for<0, NP>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            int32_t dh[2];
+            static_for<0, 2>([&](auto hc) {
+                constexpr int s = 2 * p + decltype(hc)::value;
+                int sum = 0;
+                if constexpr (PL.slot_k[s] >= 0) {
+                    constexpr int d = PL.slot_d[s];
+                    if constexpr (in_set(R - d)) sum += xbit(u.XU, R - d);
+                    if constexpr (in_set(R + d)) sum += xbit(u.XU, R + d);
+                }
+                dh[decltype(hc)::value] = -xr * g_of(s) * sum;
+            });
+            u.B[p] += (uint32_t)(dh[0] + 65536 * dh[1]);
+        });
+        static_for<0, INNER>([&](auto bc) {
+            constexpr int b = decltype(bc)::value;
+            constexpr int s = slot_of_diff(R - qpos(b));
+            if constexpr (s >= 0) {
+                constexpr int32_t unit = (s & 1) ? 65536 : 1;
+                u.Nq[b][s / 2] += -2 * xr * g_of(s) * unit;
+            }
+        });
+        u.XU ^= 1ull << (R - 1);
+    }
+
+    // Flip of inner variable b = ctz(i) at local step i (compile time).
+    template <int I>
+    __device__ static __forceinline__ void flip_inner(Uniform& u)
+    {
+        constexpr int b = ctz_ce(I);
+        constexpr int xb = xval_state(state(I - 1), b);  // before the flip
+        static_for<0, NP>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int32_t c = inner_const_pair(I, p);
+            if constexpr (xb < 0) {
+                u.B[p] += (uint32_t)u.Nq[b][p];
+                if constexpr (c != 0) u.B[p] += (uint32_t)c;
+            } else {
+                u.B[p] -= (uint32_t)u.Nq[b][p];
+                if constexpr (c != 0) u.B[p] -= (uint32_t)c;
+            }
+        });
+        u.XU ^= 1ull << (qpos(b) - 1);
+    }
+
+    template <int LO>
+    __device__ static __forceinline__ void flip_walk_bit(Uniform& u, int bit)
+    {
+        if constexpr (LO < W) {
+            if (bit == LO) flip_outer<2 + LO>(u);
+            else flip_walk_bit<LO + 1>(u, bit);
+        }
+    }
+
+    // Term at the current state: acc += sign * prod_k f'_k (mod p_i).
+    template <bool NEG>
+    __device__ static __forceinline__ void term(const uint32_t (&A)[NP], const Uniform& u, const double (&pr)[P],
+                                                const double (&pinv)[P], double (&acc)[P])
+    {
+        uint32_t f[NP];
+        static_for<0, NP>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            f[p] = pk_add(A[p], u.B[p]);
+        });
+        double q[NQ];
+        static_for<0, NQ>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            q[i] = (double)mul_halves(pk_mul(f[2 * i], f[2 * i + 1]));
+        });
+        double g[G];
+        static_for<0, G>([&](auto gc) {
+            constexpr int gi = decltype(gc)::value;
+            constexpr int q0 = PL.qb[gi], q1 = PL.qb[gi + 1];
+            double v = q[q0];
+            static_for<q0 + 1, q1>([&](auto jc) { v *= q[decltype(jc)::value]; });
+            g[gi] = v;
+        });
+        if constexpr (G == 1) {
+            static_for<0, P>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                const double r = reduce_balanced(g[0], pr[i], pinv[i]);
+                acc[i] = NEG ? acc[i] - r : acc[i] + r;
+            });
+        } else {
+            const double h = g[0] * g[1];
+            const double l = __builtin_fma(g[0], g[1], -h);
+            static_for<0, P>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                const double s = __builtin_fma(quot_nearest(h, pinv[i]), -pr[i], h);
+                if constexpr (G == 2) {
+                    acc[i] = NEG ? acc[i] - s : acc[i] + s;
+                    acc[i] = NEG ? acc[i] - l : acc[i] + l;
+                } else {
+                    double r = s + l;
+                    static_for<2, G>([&](auto gc) {
+                        constexpr int gi = decltype(gc)::value;
+                        const double h2 = r * g[gi];
+                        const double l2 = __builtin_fma(r, g[gi], -h2);
+                        const double s2 = __builtin_fma(quot_nearest(h2, pinv[i]), -pr[i], h2);
+                        if constexpr (gi == G - 1) {
+                            acc[i] = NEG ? acc[i] - s2 : acc[i] + s2;
+                            acc[i] = NEG ? acc[i] - l2 : acc[i] + l2;
+                        } else {
+                            r = s2 + l2;
+                        }
+                    });
+                }
+            });
+        }
+    }
+};
+
+// One chunk (chunk id, 2^jb jobs) evaluated by the calling wavefront.
+// Returns in every lane the wave's residues (balanced, exact fp64 integers).
+template <int V, int N, int P, int INNER>
+__device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const double (&pr)[P], const double (&pinv)[P],
+                                               double (&res)[P])
+{
+    using K = ExactV2<V, N, P, INNER>;
+    constexpr PlanCE PL = K::PL;
+    constexpr int NP = K::NP;
+    constexpr int W = K::W;
+    constexpr int M = K::M;
+    constexpr int D = K::D;
+
+    const int lane = threadIdx.x & 63;
+    // lane variables
+    uint64_t XL = 0;
+    static_for<0, 6>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        constexpr int p = PL.pos[M - 6 + b];
+        XL |= (uint64_t)((lane >> b) & 1) << (p - 1);
+    });
+    const int lane_parity = __builtin_popcount(lane) & 1;
+
+    double acc_tot[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) acc_tot[i] = 0.0;
+
+    const uint64_t njobs = 1ull << jb;
+    const uint64_t xu_chunk = chunk << (1 + W + jb);
+    for (uint64_t j = 0; j < njobs; ++j) {
+        typename K::Uniform u;
+        u.XU = xu_chunk | (j << (1 + W));
+        K::init_uniform(u);
+        // per-lane part A of every slot (pairs touching a lane variable)
+        uint32_t A[NP];
+        const uint64_t X = u.XU | XL;
+        static_for<0, NP>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            int32_t ah[2];
+            static_for<0, 2>([&](auto hc) {
+                constexpr int s = 2 * p + decltype(hc)::value;
+                if constexpr (PL.slot_k[s] < 0) {
+                    ah[decltype(hc)::value] = 1;
+                } else {
+                    constexpr uint64_t ml = K::mask_lane(s);
+                    constexpr int d = PL.slot_d[s];
+                    const int Av = K::popc_ce(ml) - 2 * (int)__builtin_popcountll((X ^ (X >> d)) & ml);
+                    if constexpr (PL.slot_halve[s]) {
+                        constexpr int c = K::popc_ce(K::mask_unif(s)) & 1;
+                        ah[decltype(hc)::value] = (Av + c) >> 1;
+                    } else {
+                        ah[decltype(hc)::value] = Av;
+                    }
+                }
+            });
+            A[p] = ((uint32_t)(ah[0] - (int32_t)kHalfBias) & 0xFFFFu) |
+                   ((uint32_t)(ah[1] - (int32_t)kHalfBias) << 16);
+        });
+        const int neg0 = (__builtin_popcountll(u.XU) + lane_parity) & 1;
+
+        double acc[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) acc[i] = 0.0;
+        constexpr uint64_t nblocks = 1ull << (W - (INNER + 1));
+        for (uint64_t ds = 0; ds < nblocks; ++ds) {
+            if (ds > 0) K::template flip_walk_bit<INNER + 1>(u, INNER + 1 + (int)__builtin_ctzll(ds));
+            static_for<0, D>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if constexpr (i > 0) {
+                    if constexpr (K::ctz_ce(i) < INNER) K::template flip_inner<i>(u);
+                    else K::template flip_outer<2 + INNER>(u);
+                }
+                K::template term<(i & 1) != 0>(A, u, pr, pinv, acc);
+            });
+            static_for<0, P>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                acc[i] = reduce_balanced(acc[i], pr[i], pinv[i]);
+            });
+        }
+        static_for<0, P>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            acc_tot[i] = reduce_balanced(neg0 ? acc_tot[i] - acc[i] : acc_tot[i] + acc[i], pr[i], pinv[i]);
+        });
+    }
+    static_for<0, P>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        res[i] = wave_sum_f64(acc_tot[i]);
+    });
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
+{
+    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
+           (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
+}
+
+template <int V, int N, int P, int INNER>
+__global__ void __launch_bounds__(256) exact_v2_kernel(const ExactArgsV2 a, double* __restrict__ out)
+{
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= a.n_waves) return;
+    const uint64_t chunk = uniform_u64(a.chunk_ids ? a.chunk_ids[wave] : a.chunk_base + wave);
+    double pr[P], pinv[P], res[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        pr[i] = a.prime[i];
+        pinv[i] = a.pinv[i];
+    }
+    exact_v2_chunk<V, N, P, INNER>(chunk, a.job_bits_per_chunk, pr, pinv, res);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) out[wave * P + i] = res[i];
+    }
+}
+
+}  // namespace sk
+

@@ -3,16 +3,25 @@
 // Implements the C ABI declared in include/skolem.h.
 #include <hip/hip_runtime.h>
 
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
 #include "../../include/skolem.h"
 #include "sk_internal.h"
+#include "sk_plan.h"
+#include "sk_batch.h"
 
 namespace sk {
 
@@ -26,6 +35,14 @@ ExactKernelFn exact_v1_lookup(int nq, int g);
 static thread_local std::string g_last_error;
 static thread_local int g_device = 0;
 static thread_local sk_stats g_stats;
+
+const char* set_last_error(const std::string& msg)
+{
+    g_last_error = msg;
+    return g_last_error.c_str();
+}
+
+int current_device() { return g_device; }
 
 static sk_status hip_fail(hipError_t e, const char* what)
 {
@@ -160,6 +177,7 @@ struct Plan {
     uint64_t pset = 0;
     int n_lane = 0, n_walk = 0, n_job = 0;
     int nq = 0, G = 0;
+    int qb[5] = {};          // product group g covers quads [qb[g], qb[g+1])
     int halved = 0;          // number of factors stored as f_k / 2
     SlotDesc slot[kMaxSlots];
     bool zero_factor = false;  // some f_k is identically 0 (no pairs at that distance)
@@ -173,112 +191,36 @@ static bool existence(int n, int v)
     return r == 2 || r == 3;
 }
 
-static int max_walk_bits(const Plan& P, int walk_cap)
-{
-    // Walked variables (ranks 1..w) must share no pair with a lane variable:
-    // pos[w] + d_max < pos[m - n_lane].  Later kernels rely on it.
-    const int dmax = P.d[P.n - 1];
-    int w = 0;
-    while (w + 1 <= P.m - 1 - P.n_lane && w + 1 <= walk_cap &&
-           P.pos[w + 1] + dmax < P.pos[P.m - P.n_lane])
-        ++w;
-    return w;
-}
-
-static sk_status make_plan(int n, int variant, Plan& P, int walk_cap = 20)
+static sk_status make_plan(int n, int variant, Plan& P)
 {
     if (variant < 0 || variant > 2) return SK_EINVAL;
     if (n < 1 || n > kMaxN || (variant == SK_HOOKED && n > kMaxN - 1)) return SK_EINVAL;
-    P.n = n;
-    P.variant = variant;
-    const int top = variant == SK_HOOKED ? 2 * n + 1 : 2 * n;
-    P.m = 0;
-    for (int p = 1; p <= top; ++p) {
-        if (variant == SK_HOOKED && p == 2 * n) continue;
-        P.pos[P.m++] = p;
-        P.pset |= 1ull << (p - 1);
+    const PlanCE C = make_plan_ce(n, variant);
+    if (!C.ok) return SK_ENOLIB;
+    P.n = C.n;
+    P.variant = C.variant;
+    P.m = C.m;
+    for (int i = 0; i < C.m; ++i) P.pos[i] = C.pos[i];
+    for (int k = 0; k < n; ++k) P.d[k] = C.d[k];
+    P.pset = C.pset;
+    P.n_lane = C.n_lane;
+    P.n_walk = C.n_walk;
+    P.n_job = C.n_job;
+    P.nq = C.nq;
+    P.G = C.G;
+    for (int g = 0; g < 5; ++g) P.qb[g] = C.qb[g];
+    P.halved = C.halved;
+    P.zero_factor = false;
+    for (int s = 0; s < kMaxSlots; ++s) {
+        if (s < 4 * C.nq && C.slot_k[s] >= 0) {
+            P.slot[s] = SlotDesc{C.slot_mask[s], C.slot_d[s], C.slot_len[s], C.slot_halve[s], C.slot_k[s]};
+            if (C.slot_len[s] == 0) P.zero_factor = true;
+        } else {
+            P.slot[s] = SlotDesc{0, 0, 1, 0, -1};
+        }
     }
-    for (int k = 1; k <= n; ++k) P.d[k - 1] = variant == SK_LANGFORD ? k + 1 : k;
-    P.n_lane = std::min(kLaneBits, P.m - 1);
-    P.n_walk = max_walk_bits(P, walk_cap);
-    P.n_job = P.m - 1 - P.n_lane - P.n_walk;
-
-    // Factor descriptors and bounds.
-    struct Fac { int k; uint64_t mask; int len, halve; uint64_t bound; };
-    std::vector<Fac> fac;
-    for (int k = 0; k < n; ++k) {
-        Fac f{};
-        f.k = k;
-        for (int p = 1; p + P.d[k] <= top; ++p) {
-            if (((P.pset >> (p - 1)) & 1) && ((P.pset >> (p + P.d[k] - 1)) & 1)) {
-                f.mask |= 1ull << (p - 1);
-                ++f.len;
-            }
-        }
-        f.halve = (f.len % 2 == 0 && f.len > 0) ? 1 : 0;
-        f.bound = (uint64_t)(f.len >> f.halve);
-        if (f.len == 0) P.zero_factor = true;
-        fac.push_back(f);
-    }
-    P.halved = 0;
-    for (auto& f : fac) P.halved += f.halve;
-
-    // Group factors: quads of 4 slots, G groups of consecutive quads.  Try the
-    // smallest G whose exactness bounds hold; factors placed greedily (largest
-    // bound first into the group with the smallest product so far).
-    P.nq = (n + 3) / 4;
-    std::vector<Fac> order = fac;
-    std::sort(order.begin(), order.end(), [](const Fac& a, const Fac& b) { return a.bound > b.bound; });
-    for (int G = 1; G <= std::min(4, P.nq); ++G) {
-        std::vector<std::vector<Fac>> grp(G);
-        std::vector<double> lg(G, 0.0);
-        std::vector<int> cap(G);
-        for (int g = 0; g < G; ++g) cap[g] = 4 * (quad_begin(P.nq, G, g + 1) - quad_begin(P.nq, G, g));
-        bool ok = true;
-        for (auto& f : order) {
-            int best = -1;
-            for (int g = 0; g < G; ++g) {
-                if ((int)grp[g].size() < cap[g] && (best < 0 || lg[g] < lg[best])) best = g;
-            }
-            if (best < 0) { ok = false; break; }
-            grp[best].push_back(f);
-            lg[best] += std::log2((double)std::max<uint64_t>(f.bound, 1));
-        }
-        if (!ok) continue;
-        // exact bound checks
-        std::vector<u128> gb(G, 1);
-        for (int g = 0; g < G; ++g)
-            for (auto& f : grp[g]) gb[g] *= std::max<uint64_t>(f.bound, 1);
-        const u128 two53 = (u128)1 << 53, two50 = (u128)1 << 50, two96 = (u128)1 << 96;
-        for (int g = 0; g < G; ++g) {
-            if (gb[g] >= two53) ok = false;
-            if (g >= 2 && gb[g] >= two50) ok = false;
-        }
-        if (ok && G >= 2) {
-            // gb[0] * gb[1] < 2^96, computed without overflow
-            const u128 a = gb[0], b = gb[1];
-            if (a != 0 && b > two96 / a) ok = false;
-        }
-        if (!ok) continue;
-        P.G = G;
-        int s = 0;
-        for (int g = 0; g < G; ++g) {
-            const int end = 4 * quad_begin(P.nq, G, g + 1);
-            for (auto& f : grp[g]) {
-                P.slot[s].mask = f.mask;
-                P.slot[s].d = P.d[f.k];
-                P.slot[s].len = f.len;
-                P.slot[s].halve = f.halve;
-                P.slot[s].pad = f.k;
-                ++s;
-            }
-            for (; s < end; ++s) P.slot[s] = SlotDesc{0, 0, 1, 0, -1};
-        }
-        return SK_OK;
-    }
-    return SK_ENOLIB;
+    return SK_OK;
 }
-
 
 // ------------------------------------------------------------------ device
 
@@ -324,9 +266,45 @@ struct SumRequest {
     size_t nchunks = 0;
     int chunk_bits = -1;
     hipStream_t stream = nullptr;
+    int kernel = 0;  // 0 best, 1 reference, 2 tuned
     sk_progress_fn progress = nullptr;
     void* progress_ctx = nullptr;
 };
+
+// ------------------------------------------------------------------ kernels
+
+using ExactV2Fn = void (*)(const ExactArgsV2, double*);
+
+struct V2Entry {
+    ExactV2Fn fn = nullptr;
+    int nprimes = 0;
+    int inner = 0;
+};
+
+static V2Entry& v2_slot(int variant, int n)
+{
+    static V2Entry table[3][kMaxN + 1];
+    return table[variant][n];
+}
+
+int register_exact_v2(int variant, int n, int nprimes, int inner, ExactV2Fn fn)
+{
+    if (variant < 0 || variant > 2 || n < 1 || n > kMaxN) return 0;
+    V2Entry& e = v2_slot(variant, n);
+    e.fn = fn;
+    e.nprimes = nprimes;
+    e.inner = inner;
+    return 1;
+}
+
+// Kernel body used for (plan, requested kernel): 2 = tuned (when built for
+// this instance), 1 = reference.
+static int pick_kernel(const Plan& P, int requested)
+{
+    if (requested == 1) return 1;
+    if (v2_slot(P.variant, P.n).fn) return 2;
+    return requested == 2 ? -1 : 1;
+}
 
 // Runs the kernel over the requested chunks.  Total mode: out has one residue
 // per prime (sum over all chunks).  Listed mode: out has nchunks x nprimes.
@@ -335,27 +313,23 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
 {
     const Plan& P = *R.plan;
     const int np = (int)R.primes.size();
-    if (np < 1 || np > kMaxPrimes) return SK_EINVAL;
+    if (np < 1 || np > 2 * kMaxPrimes) return SK_EINVAL;
     for (uint64_t p : R.primes) {
         if ((double)p <= kPrimeLo || (double)p >= kPrimeHi || !(p & 1)) return SK_EINVAL;
     }
-    ExactKernelFn fn = exact_v1_lookup(P.nq, P.G);
-    if (!fn) return SK_ENOLIB;
-
-    ExactArgs a;
-    std::memset(&a, 0, sizeof(a));
-    for (int s = 0; s < kMaxSlots; ++s) a.slot[s] = (s < 4 * P.nq) ? P.slot[s] : SlotDesc{0, 0, 1, 0, -1};
-    for (int i = 0; i < P.m; ++i) a.var_pos[i] = P.pos[i];
-    for (int i = 0; i < np; ++i) {
-        a.prime[i] = (double)R.primes[i];
-        a.pinv[i] = 1.0 / (double)R.primes[i];
+    const int kv = pick_kernel(P, R.kernel);
+    if (kv < 0) return SK_ENOLIB;
+    ExactKernelFn fn1 = nullptr;
+    ExactV2Fn fn2 = nullptr;
+    int batch = 0;  // primes per launch
+    if (kv == 2) {
+        fn2 = v2_slot(P.variant, P.n).fn;
+        batch = v2_slot(P.variant, P.n).nprimes;
+    } else {
+        fn1 = exact_v1_lookup(P.nq, P.G);
+        if (!fn1) return SK_ENOLIB;
+        batch = std::min(np, kMaxPrimes);
     }
-    a.nprimes = np;
-    a.m = P.m;
-    a.n_lane = P.n_lane;
-    a.n_walk = P.n_walk;
-    a.n_job = P.n_job;
-    a.lane_valid_bits = P.n_lane;
 
     const bool listed = R.chunk_ids != nullptr;
     int jb;
@@ -377,9 +351,9 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
         jb = std::max(0, std::min(jb, P.n_job));
         nchunks = 1ull << (P.n_job - jb);
     }
-    a.job_bits_per_chunk = jb;
     const uint64_t terms_per_chunk = 1ull << (P.n_lane + P.n_walk + jb);
-    const uint64_t terms_total = nchunks * terms_per_chunk;
+    const int nbatches = (np + batch - 1) / batch;
+    const uint64_t terms_total = nchunks * terms_per_chunk * (uint64_t)nbatches;
 
     DeviceCtx* ctx;
     sk_status stt = device_ctx(&ctx);
@@ -392,13 +366,12 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
     double* d_out = nullptr;
     uint64_t* d_ids = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    std::vector<double> h_out(wpl * np);
+    std::vector<double> h_out(wpl * batch);
     sk_status status = SK_OK;
-    auto fail = [&](hipError_t e, const char* what) {
-        status = hip_fail(e, what);
-    };
     hipError_t e;
-    if ((e = hipMalloc(&d_out, wpl * np * sizeof(double))) != hipSuccess) { fail(e, "hipMalloc"); goto done; }
+    uint64_t terms_done = 0;
+    auto fail = [&](hipError_t err, const char* what) { status = hip_fail(err, what); };
+    if ((e = hipMalloc(&d_out, wpl * batch * sizeof(double))) != hipSuccess) { fail(e, "hipMalloc"); goto done; }
     if (listed) {
         if ((e = hipMalloc(&d_ids, wpl * sizeof(uint64_t))) != hipSuccess) { fail(e, "hipMalloc"); goto done; }
     }
@@ -409,44 +382,86 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
     if (listed) out.assign(nchunks * np, 0);
     else out.assign(np, 0);
 
-    for (uint64_t base = 0; base < nchunks; base += wpl) {
-        const uint64_t nw = std::min<uint64_t>(wpl, nchunks - base);
-        a.n_waves = nw;
-        a.chunk_base = base;
-        a.chunk_ids = nullptr;
-        if (listed) {
-            if ((e = hipMemcpyAsync(d_ids, R.chunk_ids + base, nw * sizeof(uint64_t), hipMemcpyHostToDevice,
-                                    stream)) != hipSuccess) { fail(e, "hipMemcpyAsync"); goto done; }
-            a.chunk_ids = d_ids;
+    for (int bt = 0; bt < nbatches; ++bt) {
+        // primes of this launch batch; the last batch repeats its last prime
+        std::vector<uint64_t> bp(batch);
+        for (int i = 0; i < batch; ++i) bp[i] = R.primes[std::min(np - 1, bt * batch + i)];
+        const int live = std::min(batch, np - bt * batch);
+        ExactArgs a1;
+        ExactArgsV2 a2;
+        std::memset(&a1, 0, sizeof(a1));
+        std::memset(&a2, 0, sizeof(a2));
+        if (kv == 1) {
+            for (int s = 0; s < kMaxSlots; ++s) a1.slot[s] = (s < 4 * P.nq) ? P.slot[s] : SlotDesc{0, 0, 1, 0, -1};
+            for (int i = 0; i < P.m; ++i) a1.var_pos[i] = P.pos[i];
+            for (int i = 0; i < batch; ++i) {
+                a1.prime[i] = (double)bp[i];
+                a1.pinv[i] = 1.0 / (double)bp[i];
+            }
+            a1.nprimes = batch;
+            a1.m = P.m;
+            a1.n_lane = P.n_lane;
+            a1.n_walk = P.n_walk;
+            a1.n_job = P.n_job;
+            a1.lane_valid_bits = P.n_lane;
+            for (int g = 0; g < 5; ++g) a1.qb[g] = P.qb[g];
+            a1.job_bits_per_chunk = jb;
+        } else {
+            for (int i = 0; i < batch; ++i) {
+                a2.prime[i] = (double)bp[i];
+                a2.pinv[i] = 1.0 / (double)bp[i];
+            }
+            a2.job_bits_per_chunk = jb;
         }
-        const unsigned blocks = (unsigned)((nw + 3) / 4);
-        if ((e = hipEventRecord(e0, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
-        hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, stream, a, d_out);
-        if ((e = hipGetLastError()) != hipSuccess) { fail(e, "kernel launch"); goto done; }
-        if ((e = hipEventRecord(e1, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
-        if ((e = hipMemcpyAsync(h_out.data(), d_out, nw * np * sizeof(double), hipMemcpyDeviceToHost,
-                                stream)) != hipSuccess) { fail(e, "hipMemcpyAsync"); goto done; }
-        if ((e = hipStreamSynchronize(stream)) != hipSuccess) { fail(e, "hipStreamSynchronize"); goto done; }
-        float ms = 0.f;
-        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { fail(e, "hipEventElapsedTime"); goto done; }
-        st.kernel_ms += ms;
-        st.launches += 1;
-        for (uint64_t w = 0; w < nw; ++w) {
-            for (int i = 0; i < np; ++i) {
-                const uint64_t r = fp_to_residue(h_out[w * np + i], R.primes[i]);
-                if (listed) out[(base + w) * np + i] = r;
-                else out[i] = (uint64_t)(((u128)out[i] + r) % R.primes[i]);
+        for (uint64_t base = 0; base < nchunks; base += wpl) {
+            const uint64_t nw = std::min<uint64_t>(wpl, nchunks - base);
+            const uint64_t* ids = nullptr;
+            if (listed) {
+                if ((e = hipMemcpyAsync(d_ids, R.chunk_ids + base, nw * sizeof(uint64_t), hipMemcpyHostToDevice,
+                                        stream)) != hipSuccess) { fail(e, "hipMemcpyAsync"); goto done; }
+                ids = d_ids;
+            }
+            const unsigned blocks = (unsigned)((nw + 3) / 4);
+            if ((e = hipEventRecord(e0, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
+            if (kv == 1) {
+                a1.n_waves = nw;
+                a1.chunk_base = base;
+                a1.chunk_ids = ids;
+                hipLaunchKernelGGL(fn1, dim3(blocks), dim3(256), 0, stream, a1, d_out);
+            } else {
+                a2.n_waves = nw;
+                a2.chunk_base = base;
+                a2.chunk_ids = ids;
+                hipLaunchKernelGGL(fn2, dim3(blocks), dim3(256), 0, stream, a2, d_out);
+            }
+            if ((e = hipGetLastError()) != hipSuccess) { fail(e, "kernel launch"); goto done; }
+            if ((e = hipEventRecord(e1, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
+            if ((e = hipMemcpyAsync(h_out.data(), d_out, nw * batch * sizeof(double), hipMemcpyDeviceToHost,
+                                    stream)) != hipSuccess) { fail(e, "hipMemcpyAsync"); goto done; }
+            if ((e = hipStreamSynchronize(stream)) != hipSuccess) { fail(e, "hipStreamSynchronize"); goto done; }
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { fail(e, "hipEventElapsedTime"); goto done; }
+            st.kernel_ms += ms;
+            st.launches += 1;
+            for (uint64_t w = 0; w < nw; ++w) {
+                for (int i = 0; i < live; ++i) {
+                    const int gi = bt * batch + i;
+                    const uint64_t r = fp_to_residue(h_out[w * batch + i], R.primes[gi]);
+                    if (listed) out[(base + w) * np + gi] = r;
+                    else out[gi] = (uint64_t)(((u128)out[gi] + r) % R.primes[gi]);
+                }
+            }
+            terms_done += nw * terms_per_chunk;
+            if (R.progress && R.progress(R.progress_ctx, terms_done, terms_total)) {
+                status = SK_EABORTED;
+                goto done;
             }
         }
-        if (R.progress && R.progress(R.progress_ctx, (base + nw) * terms_per_chunk, terms_total)) {
-            status = SK_EABORTED;
-            goto done;
-        }
     }
-    st.terms += terms_total;
+    st.terms += nchunks * terms_per_chunk;
     st.chunks += nchunks;
     st.log2_chunk_terms = P.n_lane + P.n_walk + jb;
-    st.kernel_variant = 1;
+    st.kernel_variant = kv;
 done:
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -455,22 +470,269 @@ done:
     return status;
 }
 
-static int primes_needed(int n)
-{
-    // C <= n! (the leftmost uncovered position always starts a new pair, so a
-    // pairing is fixed by a sequence of distinct labels); want prod p > n! 2^8
-    // with every prime above 2^45.
-    double bits = 8.0;
-    for (int i = 2; i <= n; ++i) bits += std::log2((double)i);
-    int k = (int)std::ceil(bits / 45.0);
-    return std::max(1, std::min(k, kMaxPrimes));
-}
+static int primes_needed(int n) { return primes_for(n); }
 
 static uint64_t inv_pow2_scaled(uint64_t h, int e, uint64_t p)
 {
     // h * 2^{-e} mod p
     const uint64_t inv2 = (p + 1) / 2;
     return mulmod(h, powmod(inv2, (uint64_t)e, p), p);
+}
+
+// Kernel-sum residues (halved factors) -> ordered count, with the range check.
+static sk_status residues_to_count(const Plan& P, const std::vector<uint64_t>& primes, std::vector<uint64_t> res,
+                                   Big& out)
+{
+    // C = H / 2^{m-1} with H = 2^{halved} * (kernel sum)
+    for (size_t i = 0; i < primes.size(); ++i) res[i] = inv_pow2_scaled(res[i], P.m - 1 - P.halved, primes[i]);
+    Big c = crt(res, primes);
+    if (c.cmp(factorial_big(P.n)) > 0 || !c.fits128()) {
+        g_last_error = "CRT result exceeds the bound n!";
+        return SK_ECHECK;
+    }
+    out = c;
+    return SK_OK;
+}
+
+static sk_status halve_reported(int n, int variant, unsigned flags, u128& result)
+{
+    if (!(flags & SK_ORDERED) && variant != SK_HOOKED && n > 1) {
+        if (result & 1) {
+            g_last_error = "ordered count is odd; reflections must pair up";
+            return SK_ECHECK;
+        }
+        result >>= 1;
+    }
+    return SK_OK;
+}
+
+}  // namespace sk
+
+
+namespace sk {
+
+// ------------------------------------------------------------------ batch
+
+hipError_t launch_exact_batch(unsigned blocks, hipStream_t stream, const BatchArgs& a);
+
+static int batch_kind(int variant, int n)
+{
+#define SK_BATCH_KIND(KIND, V, N) \
+    if (variant == V && n == N) return KIND;
+    SK_BATCH_CASES(SK_BATCH_KIND)
+#undef SK_BATCH_KIND
+    return -1;
+}
+
+struct BatchJob {
+    const Plan* plan;
+    std::vector<uint64_t> primes;  // primes_for(n) of them
+    std::vector<uint64_t> res;     // out: kernel-sum residues
+    uint64_t terms = 0;
+};
+
+// One persistent launch over the chunks of every job.  probe_shift > 0 runs
+// only the first 2^-probe_shift of each job's chunks (used by the autotuner).
+static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t waves, hipStream_t stream,
+                           int probe_shift, sk_stats& st, double* kernel_ms)
+{
+    if (jobs.empty()) return SK_OK;
+    if ((int)jobs.size() > kBatchMaxInstances) return SK_EINVAL;
+    DeviceCtx* ctx;
+    sk_status s = device_ctx(&ctx);
+    if (s != SK_OK) return s;
+    if (!stream) stream = ctx->stream;
+
+    BatchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    std::vector<uint64_t> items;
+    // largest chunk count first, so the short instances fill the tail
+    std::vector<size_t> order(jobs.size());
+    for (size_t i = 0; i < jobs.size(); ++i) order[i] = i;
+    std::vector<uint64_t> nch(jobs.size());
+    for (size_t b = 0; b < jobs.size(); ++b) {
+        const Plan& P = *jobs[b].plan;
+        const int kind = batch_kind(P.variant, P.n);
+        if (kind < 0 || (int)jobs[b].primes.size() != primes_for(P.n)) return SK_ENOLIB;
+        int jb = log2_chunk - P.n_lane - P.n_walk;
+        jb = std::max(0, std::min(jb, P.n_job));
+        a.inst[b].kind = kind;
+        a.inst[b].jb = jb;
+        for (size_t i = 0; i < jobs[b].primes.size(); ++i) {
+            a.inst[b].prime[i] = (double)jobs[b].primes[i];
+            a.inst[b].pinv[i] = 1.0 / (double)jobs[b].primes[i];
+        }
+        uint64_t total = 1ull << (P.n_job - jb);
+        uint64_t use = std::max<uint64_t>(1, total >> probe_shift);
+        nch[b] = use;
+        jobs[b].terms = use << (P.n_lane + P.n_walk + jb);
+    }
+    std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+        return (jobs[x].terms / nch[x]) > (jobs[y].terms / nch[y]);
+    });
+    for (size_t b : order)
+        for (uint64_t ch = 0; ch < nch[b]; ++ch) items.push_back(((uint64_t)b << kBatchChunkBits) | ch);
+    if (items.size() >= (1ull << 32)) return SK_EINVAL;
+
+    uint64_t* d_items = nullptr;
+    double* d_out = nullptr;
+    uint32_t* d_counter = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<double> h_out(items.size() * kMaxPrimes);
+    hipError_t e;
+    sk_status status = SK_OK;
+    auto fail = [&](hipError_t err, const char* what) { status = hip_fail(err, what); };
+    const unsigned blocks = (unsigned)std::max<uint64_t>(1, (waves + 3) / 4);
+    float ms = 0.f;
+    if ((e = hipMalloc(&d_items, items.size() * sizeof(uint64_t))) != hipSuccess) { fail(e, "hipMalloc"); goto done; }
+    if ((e = hipMalloc(&d_out, h_out.size() * sizeof(double))) != hipSuccess) { fail(e, "hipMalloc"); goto done; }
+    if ((e = hipMalloc(&d_counter, sizeof(uint32_t))) != hipSuccess) { fail(e, "hipMalloc"); goto done; }
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        fail(e, "hipEventCreate");
+        goto done;
+    }
+    if ((e = hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
+                            stream)) != hipSuccess) { fail(e, "hipMemcpyAsync"); goto done; }
+    if ((e = hipMemsetAsync(d_counter, 0, sizeof(uint32_t), stream)) != hipSuccess) { fail(e, "hipMemsetAsync"); goto done; }
+    a.items = d_items;
+    a.n_items = items.size();
+    a.counter = d_counter;
+    a.out = d_out;
+    if ((e = hipEventRecord(e0, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
+    if ((e = launch_exact_batch(blocks, stream, a)) != hipSuccess) { fail(e, "batch launch"); goto done; }
+    if ((e = hipEventRecord(e1, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
+    if ((e = hipMemcpyAsync(h_out.data(), d_out, h_out.size() * sizeof(double), hipMemcpyDeviceToHost, stream)) !=
+        hipSuccess) { fail(e, "hipMemcpyAsync"); goto done; }
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) { fail(e, "hipStreamSynchronize"); goto done; }
+    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { fail(e, "hipEventElapsedTime"); goto done; }
+    for (auto& j : jobs) j.res.assign(j.primes.size(), 0);
+    for (size_t it = 0; it < items.size(); ++it) {
+        const size_t b = (size_t)(items[it] >> kBatchChunkBits);
+        BatchJob& j = jobs[b];
+        for (size_t i = 0; i < j.primes.size(); ++i) {
+            const uint64_t r = fp_to_residue(h_out[it * kMaxPrimes + i], j.primes[i]);
+            j.res[i] = (uint64_t)(((u128)j.res[i] + r) % j.primes[i]);
+        }
+    }
+    if (kernel_ms) *kernel_ms = ms;
+    st.kernel_ms += ms;
+    st.launches += 1;
+    st.chunks += items.size();
+    for (auto& j : jobs) st.terms += j.terms;
+    st.log2_chunk_terms = log2_chunk;
+    st.kernel_variant = 3;
+done:
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (d_items) (void)hipFree(d_items);
+    if (d_out) (void)hipFree(d_out);
+    if (d_counter) (void)hipFree(d_counter);
+    return status;
+}
+
+// ----- autotune cache: (arch, CUs, instance list) -> (log2_chunk, waves)
+
+static std::mutex g_tune_mu;
+static std::map<std::string, std::pair<int, uint64_t>> g_tune;
+static bool g_tune_loaded = false;
+
+static std::string tune_path()
+{
+    const char* p = std::getenv("SK_TUNE_CACHE");
+    if (p && *p) return p;
+    const char* h = std::getenv("HOME");
+    return std::string(h ? h : "/tmp") + "/.cache/skolem_mi355x_tune.txt";
+}
+
+static void tune_load()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    std::ifstream f(tune_path());
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string key;
+        int lc;
+        uint64_t w;
+        if (is >> key >> lc >> w) g_tune[key] = {lc, w};
+    }
+}
+
+static void tune_store()
+{
+    const std::string path = tune_path();
+    const size_t slash = path.find_last_of('/');
+    if (slash != std::string::npos) {
+        std::string dir = path.substr(0, slash);
+        std::string cmd;  // create the directory without a shell
+        for (size_t i = 1; i <= dir.size(); ++i) {
+            if (i == dir.size() || dir[i] == '/') {
+                std::string sub = dir.substr(0, i);
+                (void)::mkdir(sub.c_str(), 0755);
+            }
+        }
+    }
+    std::ofstream f(path, std::ios::trunc);
+    for (auto& kv : g_tune) f << kv.first << " " << kv.second.first << " " << kv.second.second << "\n";
+}
+
+static std::string tune_key(const std::vector<const Plan*>& plans)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, g_device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        cus = prop.multiProcessorCount;
+    }
+    for (auto& ch : arch)
+        if (ch == ' ' || ch == ':') ch = '_';
+    std::ostringstream os;
+    os << arch << "|" << cus;
+    std::vector<std::string> names;
+    for (auto* p : plans) names.push_back(std::to_string(p->variant) + "." + std::to_string(p->n));
+    std::sort(names.begin(), names.end());
+    for (auto& nm : names) os << "|" << nm;
+    return os.str();
+}
+
+// Times the batch on 1/16 of every instance for each candidate shape and
+// keeps the fastest (sign vectors per second).
+static sk_status autotune(const std::vector<const Plan*>& plans, hipStream_t stream, int* best_lc,
+                          uint64_t* best_w, double* best_rate)
+{
+    DeviceCtx* ctx;
+    sk_status s = device_ctx(&ctx);
+    if (s != SK_OK) return s;
+    const int lcs[] = {24, 26, 28, 30};
+    const int wps[] = {1, 2, 3, 4};
+    double best = -1.0;
+    for (int lc : lcs) {
+        for (int wp : wps) {
+            std::vector<BatchJob> jobs;
+            for (auto* p : plans) {
+                BatchJob j;
+                j.plan = p;
+                j.primes = default_primes(primes_for(p->n), 0);
+                jobs.push_back(j);
+            }
+            sk_stats st;
+            std::memset(&st, 0, sizeof(st));
+            double ms = 0;
+            const uint64_t waves = (uint64_t)ctx->cus * 4 * wp;
+            s = run_batch(jobs, lc, waves, stream, 4, st, &ms);
+            if (s != SK_OK) return s;
+            const double rate = (double)st.terms / (ms * 1e-3);
+            if (rate > best) {
+                best = rate;
+                *best_lc = lc;
+                *best_w = waves;
+            }
+        }
+    }
+    if (best_rate) *best_rate = best;
+    return SK_OK;
 }
 
 }  // namespace sk
@@ -511,19 +773,16 @@ static sk_status count_impl(int n, int variant, unsigned flags, const sk_tuning*
             R.primes = default_primes(np, pass * np);
             R.log2_chunk_terms = (tune && tune->log2_chunk_terms > 0) ? tune->log2_chunk_terms : 0;
             R.waves_per_launch = tune ? tune->waves_per_launch : 0;
+            R.kernel = tune ? tune->kernel : 0;
             R.stream = (hipStream_t)stream;
             R.progress = progress;
             R.progress_ctx = pctx;
             std::vector<uint64_t> res;
             s = run_sum(R, res, st);
             if (s != SK_OK) return s;
-            // C = H / 2^{m-1} with H = 2^{halved} * (kernel sum)
-            for (int i = 0; i < np; ++i) res[i] = inv_pow2_scaled(res[i], P.m - 1 - P.halved, R.primes[i]);
-            Big c = crt(res, R.primes);
-            if (c.cmp(factorial_big(n)) > 0 || !c.fits128()) {
-                g_last_error = "CRT result exceeds the bound n!";
-                return SK_ECHECK;
-            }
+            Big c;
+            s = residues_to_count(P, R.primes, res, c);
+            if (s != SK_OK) return s;
             if (pass == 0) first = c;
             else if (c.cmp(first) != 0) {
                 g_last_error = "verification pass with disjoint primes disagrees";
@@ -535,13 +794,8 @@ static sk_status count_impl(int n, int variant, unsigned flags, const sk_tuning*
         st.passes = passes;
         result = ((u128)first.w[1] << 64) | first.w[0];
     }
-    if (!(flags & SK_ORDERED) && variant != SK_HOOKED && n > 1) {
-        if (result & 1) {
-            g_last_error = "ordered count is odd; reflections must pair up";
-            return SK_ECHECK;
-        }
-        result >>= 1;
-    }
+    s = halve_reported(n, variant, flags, result);
+    if (s != SK_OK) return s;
     out->lo = (uint64_t)result;
     out->hi = (uint64_t)(result >> 64);
     st.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -562,10 +816,146 @@ sk_status sk_count_ex(int n, int variant, unsigned flags, const sk_tuning* tune,
     return count_impl(n, variant, flags, tune, stream, progress, progress_ctx, stats, out);
 }
 
+
+sk_status sk_count_batch(const sk_instance* inst, size_t k, const sk_tuning* tune, void* stream, sk_stats* stats,
+                         sk_u128* out)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!inst || !out || k == 0) return SK_EINVAL;
+    std::vector<Plan> plans(k);
+    for (size_t i = 0; i < k; ++i) {
+        sk_status s = make_plan(inst[i].n, inst[i].variant, plans[i]);
+        if (s != SK_OK) return s;
+    }
+    sk_stats st;
+    std::memset(&st, 0, sizeof(st));
+    std::vector<u128> result(k, 0);
+    std::vector<int> batched, separate;
+    for (size_t i = 0; i < k; ++i) {
+        const bool needed = existence(inst[i].n, inst[i].variant) || (inst[i].flags & SK_NO_SHORTCUT);
+        if (!needed) continue;
+        const bool can = batch_kind(inst[i].variant, inst[i].n) >= 0 && v2_slot(inst[i].variant, inst[i].n).fn &&
+                         !(tune && (tune->kernel == 1 || tune->primes > primes_for(inst[i].n)));
+        (can ? batched : separate).push_back((int)i);
+    }
+    if ((int)batched.size() > kBatchMaxInstances) {
+        separate.insert(separate.end(), batched.begin() + kBatchMaxInstances, batched.end());
+        batched.resize(kBatchMaxInstances);
+    }
+    if (!batched.empty()) {
+        std::vector<const Plan*> bp;
+        for (int i : batched) bp.push_back(&plans[i]);
+        int lc = 27;
+        uint64_t waves = 0;
+        DeviceCtx* ctx;
+        sk_status s = device_ctx(&ctx);
+        if (s != SK_OK) return s;
+        waves = (uint64_t)ctx->cus * 4 * 2;
+        if (tune && tune->log2_chunk_terms > 0) {
+            lc = tune->log2_chunk_terms;
+            if (tune->waves_per_launch > 0) waves = (uint64_t)tune->waves_per_launch;
+        } else {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            tune_load();
+            auto it = g_tune.find(tune_key(bp));
+            if (it != g_tune.end()) {
+                lc = it->second.first;
+                waves = it->second.second;
+            }
+        }
+        int passes = 1;
+        for (int i : batched)
+            if (inst[i].flags & SK_VERIFY) passes = 2;
+        std::vector<Big> first(k);
+        for (int pass = 0; pass < passes; ++pass) {
+            std::vector<BatchJob> jobs;
+            std::vector<int> who;
+            for (int i : batched) {
+                if (pass == 1 && !(inst[i].flags & SK_VERIFY)) continue;
+                BatchJob j;
+                j.plan = &plans[i];
+                const int np = primes_for(plans[i].n);
+                j.primes = default_primes(np, pass * np);
+                jobs.push_back(j);
+                who.push_back(i);
+            }
+            s = run_batch(jobs, lc, waves, (hipStream_t)stream, 0, st, nullptr);
+            if (s != SK_OK) return s;
+            for (size_t b = 0; b < jobs.size(); ++b) {
+                const int i = who[b];
+                Big cnt;
+                s = residues_to_count(plans[i], jobs[b].primes, jobs[b].res, cnt);
+                if (s != SK_OK) return s;
+                if (pass == 0) {
+                    first[i] = cnt;
+                    result[i] = ((u128)cnt.w[1] << 64) | cnt.w[0];
+                } else if (cnt.cmp(first[i]) != 0) {
+                    g_last_error = "verification pass with disjoint primes disagrees";
+                    return SK_ECHECK;
+                }
+            }
+        }
+        st.passes = passes;
+    }
+    for (int i : separate) {
+        sk_stats s1;
+        sk_u128 o;
+        sk_status s = count_impl(inst[i].n, inst[i].variant, inst[i].flags | SK_ORDERED, tune, stream, nullptr,
+                                 nullptr, &s1, &o);
+        if (s != SK_OK) return s;
+        result[i] = ((u128)o.hi << 64) | o.lo;
+        st.kernel_ms += s1.kernel_ms;
+        st.launches += s1.launches;
+        st.terms += s1.terms;
+        st.chunks += s1.chunks;
+    }
+    for (size_t i = 0; i < k; ++i) {
+        sk_status s = halve_reported(inst[i].n, inst[i].variant, inst[i].flags, result[i]);
+        if (s != SK_OK) return s;
+    }
+    for (size_t i = 0; i < k; ++i) {
+        out[i].lo = (uint64_t)result[i];
+        out[i].hi = (uint64_t)(result[i] >> 64);
+    }
+    st.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    st.ms_per_launch_avg = st.launches ? st.kernel_ms / (double)st.launches : 0.0;
+    g_stats = st;
+    if (stats) *stats = st;
+    return SK_OK;
+}
+
+sk_status sk_autotune_batch(const sk_instance* inst, size_t k, void* stream, sk_tuning* best, double* best_rate)
+{
+    if (!inst || k == 0 || !best) return SK_EINVAL;
+    std::vector<Plan> plans(k);
+    std::vector<const Plan*> bp;
+    for (size_t i = 0; i < k; ++i) {
+        sk_status s = make_plan(inst[i].n, inst[i].variant, plans[i]);
+        if (s != SK_OK) return s;
+        if (batch_kind(inst[i].variant, inst[i].n) < 0 || !v2_slot(inst[i].variant, inst[i].n).fn) return SK_ENOLIB;
+        bp.push_back(&plans[i]);
+    }
+    if (bp.size() > (size_t)kBatchMaxInstances) return SK_EINVAL;
+    int lc = 0;
+    uint64_t w = 0;
+    sk_status s = autotune(bp, (hipStream_t)stream, &lc, &w, best_rate);
+    if (s != SK_OK) return s;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load();
+        g_tune[tune_key(bp)] = {lc, w};
+        tune_store();
+    }
+    std::memset(best, 0, sizeof(*best));
+    best->log2_chunk_terms = lc;
+    best->waves_per_launch = (int)w;
+    return SK_OK;
+}
+
 sk_status sk_sign_sum_residues(int n, int variant, const uint64_t* primes, int nprimes,
                                const sk_tuning* tune, void* stream, uint64_t* residues)
 {
-    if (!primes || !residues || nprimes < 1 || nprimes > kMaxPrimes) return SK_EINVAL;
+    if (!primes || !residues || nprimes < 1 || nprimes > 2 * kMaxPrimes) return SK_EINVAL;
     Plan P;
     sk_status s = make_plan(n, variant, P);
     if (s != SK_OK) return s;
@@ -574,6 +964,7 @@ sk_status sk_sign_sum_residues(int n, int variant, const uint64_t* primes, int n
     R.primes.assign(primes, primes + nprimes);
     R.log2_chunk_terms = (tune && tune->log2_chunk_terms > 0) ? tune->log2_chunk_terms : 0;
     R.waves_per_launch = tune ? tune->waves_per_launch : 0;
+    R.kernel = tune ? tune->kernel : 0;
     R.stream = (hipStream_t)stream;
     std::vector<uint64_t> res;
     sk_stats st;
@@ -611,9 +1002,10 @@ sk_status sk_describe(int n, int variant, sk_plan_desc* out)
 }
 
 sk_status sk_partial_chunks(int n, int variant, int log2_chunks, const uint64_t* chunk_ids, size_t nchunks,
-                            const uint64_t* primes, int nprimes, void* stream, uint64_t* residues_out)
+                            const uint64_t* primes, int nprimes, const sk_tuning* tune, void* stream,
+                            uint64_t* residues_out)
 {
-    if (!chunk_ids || !primes || !residues_out || nprimes < 1 || nprimes > kMaxPrimes) return SK_EINVAL;
+    if (!chunk_ids || !primes || !residues_out || nprimes < 1 || nprimes > 2 * kMaxPrimes) return SK_EINVAL;
     Plan P;
     sk_status s = make_plan(n, variant, P);
     if (s != SK_OK) return s;
@@ -625,6 +1017,8 @@ sk_status sk_partial_chunks(int n, int variant, int log2_chunks, const uint64_t*
     R.chunk_ids = chunk_ids;
     R.nchunks = nchunks;
     R.chunk_bits = log2_chunks;
+    R.waves_per_launch = tune ? tune->waves_per_launch : 0;
+    R.kernel = tune ? tune->kernel : 0;
     R.stream = (hipStream_t)stream;
     std::vector<uint64_t> res;
     sk_stats st;
@@ -676,6 +1070,7 @@ const char* sk_kernel_name(int kernel_variant)
     switch (kernel_variant) {
         case 1: return "exact_v1_kernel";
         case 2: return "exact_v2_kernel";
+        case 3: return "exact_batch_kernel";
     }
     return "none";
 }

@@ -1,0 +1,212 @@
+// Parallel tempering for the approximate count (Sec. 3, Algorithm 2) on gfx950.
+//
+// One wavefront runs one ladder: lane j is inverse temperature beta_j (j < M
+// <= 64).  Every lane owns one configuration slot in LDS -- the placements a_k
+// of the n pairs (bytes) and the occupancy of every bin (bytes) -- and its
+// energy E (empty bins).  An exchange of neighbouring levels swaps the slot
+// indices of two lanes, which moves the whole configuration between levels.
+//
+// Per iteration (Algorithm 2's order):
+//   1. the energy histogram of every level is incremented (LDS), the exact
+//      form of Ratio(j) accumulation;
+//   2. every level proposes one move: pair k uniform, placement uniform
+//      (Sec. 3), accepted with min(1, exp(-beta_j dE));
+//   3. neighbouring levels exchange configurations with min(1,
+//      exp(-(beta_{j+1} - beta_j)(E_j - E_{j+1}))): even pairs on even
+//      iterations, odd pairs on odd iterations.
+//
+// Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the seed, one
+// block of four words per (iteration, ladder, level): word 0 picks the pair,
+// word 1 the placement, word 2 decides the move, word 3 (level j) decides the
+// exchange of (j, j+1).  Accept/reject compares the word with a threshold
+// floor(2^32 exp(-b e)) computed on the host, so the decisions are bit-exact
+// reproducible.  Initial configurations use counters (0xFFFFFFF0 + block,
+// 0xFFFFFFFF, ladder, level).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sk_pt.h"
+
+namespace sk {
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                              uint32_t k1, uint32_t (&out)[4])
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+// Placement index -> left position of pair k (1-based), for the variant's
+// position set.
+__device__ __forceinline__ int placement(const PtArgs& a, int d, int idx)
+{
+    if (a.variant == 2) {  // hooked: 1..2n-1 and 2n+1
+        const int inside = 2 * a.n - 1 - d;  // placements with both ends <= 2n-1
+        return idx < inside ? 1 + idx : 2 * a.n + 1 - d;
+    }
+    return 1 + idx;
+}
+
+__device__ __forceinline__ int pair_diff(const PtArgs& a, int k) { return a.variant == 1 ? k + 2 : k + 1; }
+
+__device__ __forceinline__ int placements_of(const PtArgs& a, int d)
+{
+    if (a.variant == 2) return d == 1 ? 2 * a.n - 2 : 2 * a.n - d;
+    return 2 * a.n - d;
+}
+
+__global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
+{
+    extern __shared__ uint8_t lds[];
+    const int lane = threadIdx.x;
+    const uint32_t ladder = a.ladder_base + blockIdx.x;
+    const int M = a.levels;
+    const int n = a.n;
+    const int top = a.top;
+    const int H = top + 1;
+    const int slot_bytes = a.slot_bytes;  // n placements + (top + 1) occupancies, rounded to 4
+    uint8_t* slots = lds;
+    uint32_t* hist = (uint32_t*)(lds + (size_t)64 * slot_bytes);  // M x H
+    const bool live = lane < M;
+
+    for (int i = lane; i < M * H; i += 64) hist[i] = 0;
+
+    int slot = lane;
+    int E = 0;
+    uint32_t T1 = 0, T2 = 0;
+    uint32_t mv_acc = 0, sw_acc = 0;
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    if (live) {
+        T1 = a.move_thr[lane * 2 + 0];
+        T2 = a.move_thr[lane * 2 + 1];
+        uint8_t* s = slots + (size_t)slot * slot_bytes;
+        uint8_t* occ = s + n;
+        for (int p = 0; p <= top; ++p) occ[p] = 0;
+        if (a.state_in) {
+            const uint8_t* src = a.state_in + ((size_t)ladder * M + lane) * n;
+            for (int k = 0; k < n; ++k) s[k] = src[k];
+        } else {
+            for (int blk = 0; blk * 4 < n; ++blk) {
+                uint32_t r[4];
+                philox4x32_10(0xFFFFFFF0u + (uint32_t)blk, 0xFFFFFFFFu, ladder, (uint32_t)lane, k0, k1, r);
+                for (int t = 0; t < 4 && blk * 4 + t < n; ++t) {
+                    const int k = blk * 4 + t;
+                    const int d = pair_diff(a, k);
+                    const int idx = (int)__umulhi(r[t], (uint32_t)placements_of(a, d));
+                    s[k] = (uint8_t)placement(a, d, idx);
+                }
+            }
+        }
+        for (int k = 0; k < n; ++k) {
+            const int d = pair_diff(a, k);
+            occ[s[k]]++;
+            occ[s[k] + d]++;
+        }
+        for (int p = 1; p <= top; ++p)
+            if (((a.pset >> (p - 1)) & 1) && occ[p] == 0) ++E;
+    }
+    __syncthreads();
+
+    for (uint64_t it = a.it_begin; it < a.it_end; ++it) {
+        // 1. record
+        if (live) hist[lane * H + E] += 1u;
+        // 2. move
+        uint32_t r[4];
+        philox4x32_10((uint32_t)it, (uint32_t)(it >> 32), ladder, (uint32_t)lane, k0, k1, r);
+        if (live) {
+            uint8_t* s = slots + (size_t)slot * slot_bytes;
+            uint8_t* occ = s + n;
+            const int k = (int)__umulhi(r[0], (uint32_t)n);
+            const int d = pair_diff(a, k);
+            const int idx = (int)__umulhi(r[1], (uint32_t)placements_of(a, d));
+            const int a_new = placement(a, d, idx);
+            const int a_old = s[k];
+            int de = 0;
+            uint8_t o;
+            o = occ[a_old];
+            occ[a_old] = o - 1;
+            de += (o == 1);
+            o = occ[a_old + d];
+            occ[a_old + d] = o - 1;
+            de += (o == 1);
+            o = occ[a_new];
+            occ[a_new] = o + 1;
+            de -= (o == 0);
+            o = occ[a_new + d];
+            occ[a_new + d] = o + 1;
+            de -= (o == 0);
+            const bool acc = de <= 0 || r[2] < (de == 1 ? T1 : T2);
+            if (acc) {
+                s[k] = (uint8_t)a_new;
+                E += de;
+                ++mv_acc;
+            } else {
+                occ[a_new]--;
+                occ[a_new + d]--;
+                occ[a_old]++;
+                occ[a_old + d]++;
+            }
+        }
+        // 3. exchange (j, j+1) with j of the iteration's parity
+        const int parity = (int)(it & 1);
+        const int E_up = __shfl_down(E, 1, 64);
+        const int slot_up = __shfl_down(slot, 1, 64);
+        const bool lower = live && lane + 1 < M && (lane & 1) == parity;
+        bool sw = false;
+        if (lower) {
+            const int de = E - E_up;
+            sw = de <= 0 || r[3] < a.swap_thr[lane * H + de];
+        }
+        const int sw_from_below = __shfl_up((int)sw, 1, 64);
+        const int E_dn = __shfl_up(E, 1, 64);
+        const int slot_dn = __shfl_up(slot, 1, 64);
+        const bool upper = live && lane >= 1 && ((lane - 1) & 1) == parity && sw_from_below;
+        if (sw) {
+            E = E_up;
+            slot = slot_up;
+            ++sw_acc;
+        } else if (upper) {
+            E = E_dn;
+            slot = slot_dn;
+        }
+    }
+    __syncthreads();
+
+    // outputs: histograms, acceptance counts, states in level order
+    for (int i = lane; i < M * H; i += 64) a.hist_out[(size_t)ladder * M * H + i] += hist[i];
+    if (live) {
+        a.move_acc[(size_t)ladder * M + lane] += mv_acc;
+        a.swap_acc[(size_t)ladder * M + lane] += sw_acc;
+        a.energy_out[(size_t)ladder * M + lane] = E;
+        const uint8_t* s = slots + (size_t)slot * slot_bytes;
+        uint8_t* dst = a.state_out + ((size_t)ladder * M + lane) * n;
+        for (int k = 0; k < n; ++k) dst[k] = s[k];
+    }
+}
+
+hipError_t launch_pt_ladders(unsigned ladders, size_t lds_bytes, hipStream_t stream, const PtArgs& a)
+{
+    hipLaunchKernelGGL(pt_ladder_kernel, dim3(ladders), dim3(64), lds_bytes, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace sk

@@ -1,0 +1,43 @@
+// Shared definitions of the persistent batched launch (host and device).
+#pragma once
+
+#include <stdint.h>
+
+#include "sk_internal.h"
+
+namespace sk {
+
+// Specialisations compiled into the persistent batched kernel:
+// X(kind, variant, n).  The set is the mixed-instance workload (Skolem n = 16,
+// 17, 20, 21; Langford n = 15, 16, 19, 20; hooked n = 14, 15).
+#define SK_BATCH_CASES(X) \
+    X(0, 0, 16)           \
+    X(1, 0, 17)           \
+    X(2, 0, 20)           \
+    X(3, 0, 21)           \
+    X(4, 1, 15)           \
+    X(5, 1, 16)           \
+    X(6, 1, 19)           \
+    X(7, 1, 20)           \
+    X(8, 2, 14)           \
+    X(9, 2, 15)
+
+constexpr int kBatchMaxInstances = 16;
+constexpr int kBatchChunkBits = 48;  // item = (instance << 48) | chunk id
+
+struct BatchInstance {
+    int32_t kind;  // case of SK_BATCH_CASES
+    int32_t jb;    // job bits enumerated inside one chunk
+    double prime[kMaxPrimes];
+    double pinv[kMaxPrimes];
+};
+
+struct BatchArgs {
+    BatchInstance inst[kBatchMaxInstances];
+    const uint64_t* items;  // device: n_items work items
+    uint64_t n_items;
+    uint32_t* counter;      // device: next item (set to 0 before the launch)
+    double* out;            // device: n_items x kMaxPrimes residues
+};
+
+}  // namespace sk

@@ -47,7 +47,19 @@ struct ExactArgs {
     const uint64_t* chunk_ids;   // device array, one chunk id per wave, or nullptr
     uint64_t n_waves;            // waves with work in this launch
     int32_t lane_valid_bits;     // lanes >= 2^lane_valid_bits contribute nothing
+    int32_t qb[5];               // product group g covers quads [qb[g], qb[g+1])
+};
+
+// Arguments of one launch of the specialised exact kernel (exact_v2.hip);
+// everything about the instance itself is compiled in.
+struct ExactArgsV2 {
+    double prime[kMaxPrimes];
+    double pinv[kMaxPrimes];
+    int32_t job_bits_per_chunk;  // low job variables enumerated inside one chunk
     int32_t pad0;
+    uint64_t chunk_base;         // chunk index of wave 0 (when chunk_ids == nullptr)
+    const uint64_t* chunk_ids;   // device array, one chunk id per wave, or nullptr
+    uint64_t n_waves;            // waves with work in this launch
 };
 
 // Quad boundaries of the product groups: group gi covers quads

@@ -1,0 +1,200 @@
+// Instance plan for the exact sum, computable at compile time (the tuned
+// kernel is specialised per (variant, n)) and at run time (the host).
+//
+// For a variant and n it fixes:
+//   * the position set P and the differences d_k (Sec. 1.1, Sec. 1.2),
+//   * the split of the 2n sign variables (ordered by position) into
+//       rank 0            x at position 1, fixed to +1 (Lemma 2.2),
+//       walk ranks        1 .. n_walk, visited in Gray-code order,
+//       job ranks         the ones between (chunk bits on top),
+//       lane ranks        the 6 highest, one combination per lane,
+//     with n_walk as large as possible such that no walked variable forms a
+//     pair (i, i + d_k) with a lane variable,
+//   * the factor slots: factor k sits in one of 4*nq slots; slots form quads
+//     and quads form G groups whose exact products stay below 2^53 (and the
+//     host-checked bounds of the modular chain hold),
+//   * which factors are stored halved (f_k is even for every x when the
+//     number of pairs L_k at distance d_k is even).
+#pragma once
+
+#include <stdint.h>
+
+#include "sk_internal.h"
+
+namespace sk {
+
+struct PlanCE {
+    bool ok = false;
+    int n = 0, variant = 0, m = 0, top = 0;
+    int pos[kMaxVars] = {};
+    int d[kMaxN] = {};
+    uint64_t pset = 0;
+    int n_lane = 0, n_walk = 0, n_job = 0;
+    int nq = 0, G = 0, halved = 0;
+    int qb[5] = {};  // group g covers quads [qb[g], qb[g+1])
+    // per slot (4*nq used); factor index -1 = constant-1 slot
+    int slot_k[kMaxSlots] = {};
+    int slot_d[kMaxSlots] = {};
+    uint64_t slot_mask[kMaxSlots] = {};
+    int slot_len[kMaxSlots] = {};
+    int slot_halve[kMaxSlots] = {};
+};
+
+constexpr int kWalkCap = 20;
+
+__host__ __device__ constexpr unsigned __int128 u128_max1(uint64_t x) { return x ? x : 1; }
+
+__host__ __device__ constexpr PlanCE make_plan_ce(int n, int variant, int walk_cap = kWalkCap)
+{
+    PlanCE P{};
+    if (variant < 0 || variant > 2) return P;
+    if (n < 1 || n > kMaxN || (variant == 2 && n > kMaxN - 1)) return P;
+    P.n = n;
+    P.variant = variant;
+    P.top = variant == 2 ? 2 * n + 1 : 2 * n;
+    for (int p = 1; p <= P.top; ++p) {
+        if (variant == 2 && p == 2 * n) continue;
+        P.pos[P.m++] = p;
+        P.pset |= 1ull << (p - 1);
+    }
+    for (int k = 1; k <= n; ++k) P.d[k - 1] = variant == 1 ? k + 1 : k;
+    P.n_lane = kLaneBits < P.m - 1 ? kLaneBits : P.m - 1;
+    {
+        const int dmax = P.d[n - 1];
+        int w = 0;
+        while (w + 1 <= P.m - 1 - P.n_lane && w + 1 <= walk_cap && P.pos[w + 1] + dmax < P.pos[P.m - P.n_lane])
+            ++w;
+        P.n_walk = w;
+    }
+    P.n_job = P.m - 1 - P.n_lane - P.n_walk;
+
+    // factors
+    uint64_t fmask[kMaxN] = {};
+    int flen[kMaxN] = {}, fhalve[kMaxN] = {};
+    uint64_t fbound[kMaxN] = {};
+    for (int k = 0; k < n; ++k) {
+        for (int p = 1; p + P.d[k] <= P.top; ++p) {
+            if (((P.pset >> (p - 1)) & 1) && ((P.pset >> (p + P.d[k] - 1)) & 1)) {
+                fmask[k] |= 1ull << (p - 1);
+                ++flen[k];
+            }
+        }
+        fhalve[k] = (flen[k] % 2 == 0 && flen[k] > 0) ? 1 : 0;
+        fbound[k] = (uint64_t)(flen[k] >> fhalve[k]);
+        P.halved += fhalve[k];
+    }
+    // factor order: bound descending, then k ascending (insertion sort)
+    int order[kMaxN] = {};
+    for (int k = 0; k < n; ++k) order[k] = k;
+    for (int i = 1; i < n; ++i) {
+        int v = order[i], j = i - 1;
+        while (j >= 0 && (fbound[order[j]] < fbound[v] || (fbound[order[j]] == fbound[v] && order[j] > v))) {
+            order[j + 1] = order[j];
+            --j;
+        }
+        order[j + 1] = v;
+    }
+    P.nq = (n + 3) / 4;
+    const unsigned __int128 two53 = (unsigned __int128)1 << 53, two50 = (unsigned __int128)1 << 50,
+                            two96 = (unsigned __int128)1 << 96;
+    for (int G = 1; G <= 4 && G <= P.nq; ++G) {
+        // every split of the nq quads into G consecutive groups (ordered sizes)
+        int sizes[4] = {1, 1, 1, 1};
+        for (;;) {
+            int tot = 0;
+            for (int g = 0; g < G; ++g) tot += sizes[g];
+            if (tot == P.nq) {
+                for (int heur = 0; heur < 2; ++heur) {
+                    int cap[4] = {}, cnt[4] = {};
+                    unsigned __int128 prod[4] = {1, 1, 1, 1};
+                    int member[4][kMaxSlots] = {};
+                    for (int g = 0; g < G; ++g) cap[g] = 4 * sizes[g];
+                    // budget (bits) per group: the first two share 96, the rest 50
+                    int budget[4] = {};
+                    for (int g = 0; g < G; ++g) budget[g] = G == 1 ? 52 : (g < 2 ? 48 : 49);
+                    bool fits = true;
+                    for (int i = 0; i < n && fits; ++i) {
+                        const int k = order[i];
+                        int best = -1;
+                        for (int g = 0; g < G; ++g) {
+                            if (cnt[g] >= cap[g]) continue;
+                            if (best < 0) {
+                                best = g;
+                                continue;
+                            }
+                            if (heur == 0) {
+                                if (prod[g] < prod[best]) best = g;
+                            } else {
+                                // most remaining budget: compare prod / 2^budget
+                                const unsigned __int128 lhs = prod[g] << (unsigned)(52 - budget[g]);
+                                const unsigned __int128 rhs = prod[best] << (unsigned)(52 - budget[best]);
+                                if (lhs < rhs) best = g;
+                            }
+                        }
+                        if (best < 0) {
+                            fits = false;
+                            break;
+                        }
+                        member[best][cnt[best]++] = k;
+                        prod[best] *= u128_max1(fbound[k]);
+                        if (prod[best] >= two53) fits = false;
+                    }
+                    if (!fits) continue;
+                    for (int g = 2; g < G; ++g)
+                        if (prod[g] >= two50) fits = false;
+                    if (fits && G >= 2 && prod[1] > two96 / prod[0]) fits = false;
+                    if (!fits) continue;
+                    P.G = G;
+                    P.qb[0] = 0;
+                    for (int g = 0; g < G; ++g) P.qb[g + 1] = P.qb[g] + sizes[g];
+                    int s = 0;
+                    for (int g = 0; g < G; ++g) {
+                        const int end = 4 * P.qb[g + 1];
+                        for (int i = 0; i < cnt[g]; ++i, ++s) {
+                            const int k = member[g][i];
+                            P.slot_k[s] = k;
+                            P.slot_d[s] = P.d[k];
+                            P.slot_mask[s] = fmask[k];
+                            P.slot_len[s] = flen[k];
+                            P.slot_halve[s] = fhalve[k];
+                        }
+                        for (; s < end; ++s) {
+                            P.slot_k[s] = -1;
+                            P.slot_d[s] = 0;
+                            P.slot_mask[s] = 0;
+                            P.slot_len[s] = 1;
+                            P.slot_halve[s] = 0;
+                        }
+                    }
+                    for (; s < kMaxSlots; ++s) {
+                        P.slot_k[s] = -1;
+                        P.slot_len[s] = 1;
+                    }
+                    P.ok = true;
+                    return P;
+                }
+            }
+            // next composition (odometer over sizes[0..G-1], each 1..nq)
+            int g = 0;
+            while (g < G && ++sizes[g] > P.nq) sizes[g++] = 1;
+            if (g == G) break;
+        }
+    }
+    return P;
+}
+
+// Fewest primes in (2^45, 2^46) whose product exceeds n! * 2^8.  Every ordered
+// count is at most n!: the leftmost uncovered position always starts a new
+// pair, so a pairing is fixed by the order in which labels are used.
+__host__ __device__ constexpr int primes_for(int n)
+{
+    // sum of log2(i) for i <= n, bounded above by integer bit lengths is too
+    // coarse; use a table of ceil(log2(n!)) for n <= 32.
+    constexpr int lg_fact[33] = {0,  0,  1,  3,  5,  7,  10, 13, 16, 19, 22, 26, 29, 33, 37, 41, 45,
+                                 49, 53, 57, 62, 66, 70, 75, 80, 84, 89, 94, 98, 103, 108, 113, 118};
+    const int bits = lg_fact[n < 0 ? 0 : (n > 32 ? 32 : n)] + 8;
+    int k = (bits + 44) / 45;
+    return k < 1 ? 1 : (k > kMaxPrimes ? kMaxPrimes : k);
+}
+
+}  // namespace sk

@@ -70,6 +70,33 @@ def test_sign_sum_residues_match_oracle(variant):
         assert got == want, (variant, n)
 
 
+@pytest.mark.parametrize("variant", ["skolem", "langford", "hooked"])
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_both_kernel_bodies_match_oracle(variant, kernel):
+    """The reference body (1) and the tuned body (2) against the oracle, on the
+    smallest instances the tuned body is built for (several unrolled blocks,
+    several jobs per chunk, every outer walked variable flipped)."""
+    for n in (13, 14):
+        _say("kernel", kernel, variant, n)
+        primes = PRIMES[:3]
+        got = sk.sign_sum_residues(n, variant, primes, tuning={"kernel": kernel})
+        want = [O.chunk_partial(n, variant, {1: 1}, p, "gray", threads=8) for p in primes]
+        assert got == want, (variant, n, kernel)
+
+
+@pytest.mark.parametrize("variant,n", [("skolem", 16), ("langford", 16), ("hooked", 15), ("skolem", 20),
+                                       ("langford", 19), ("skolem", 24)])
+def test_tuned_body_equals_reference_body_on_chunks(variant, n):
+    """Per-chunk residues of the two kernel bodies agree bit for bit (chunks
+    drawn with a seeded stream; the oracle checks the small sizes above)."""
+    c = sk.max_chunk_bits(n, variant)
+    ids = inputs.distinct_ids(1000 + n, c, 64)
+    primes = PRIMES[:2]
+    a = sk.partial_chunks(n, variant, c, ids, primes, tuning={"kernel": 1})
+    b = sk.partial_chunks(n, variant, c, ids, primes, tuning={"kernel": 2})
+    assert a == b
+
+
 def _chunk_fixed(n, variant, c, cid):
     """Fixed assignment of a chunk, from the chunk definition in skolem.h."""
     pos, _ = O.instance(n, variant)
@@ -81,13 +108,14 @@ def _chunk_fixed(n, variant, c, cid):
     return fixed
 
 
-@pytest.mark.parametrize("variant,n", [("skolem", 12), ("langford", 12), ("hooked", 11), ("skolem", 13)])
-def test_partial_chunks_match_oracle(variant, n):
+@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("variant,n", [("skolem", 12), ("langford", 13), ("hooked", 12), ("skolem", 13)])
+def test_partial_chunks_match_oracle(variant, n, kernel):
     cmax = sk.max_chunk_bits(n, variant)
     c = min(cmax, 6)
     ids = inputs.distinct_ids(42 + n, c, min(8, 1 << c))
     primes = PRIMES[:2]
-    got = sk.partial_chunks(n, variant, c, ids, primes)
+    got = sk.partial_chunks(n, variant, c, ids, primes, tuning={"kernel": kernel})
     for cid, row in zip(ids, got):
         fixed = _chunk_fixed(n, variant, c, cid)
         want = [O.chunk_partial(n, variant, fixed, p, "gray", threads=8) for p in primes]
@@ -104,10 +132,11 @@ def test_chunk_partials_sum_to_total():
         assert sum(r[i] for r in rows) % p == tot[i]
 
 
-@pytest.mark.parametrize("log2_chunk", [20, 23, 26, 31])
+@pytest.mark.parametrize("log2_chunk", [17, 20, 23, 26, 31])
 def test_launch_shape_does_not_change_result(log2_chunk):
     r = sk.count_ex(13, "skolem", tuning={"log2_chunk_terms": log2_chunk, "waves_per_launch": 64})
     assert r.count == 1520280
+    assert r.stats["kernel_variant"] == 2
 
 
 def test_repeat_runs_bit_identical():
@@ -136,6 +165,11 @@ def test_hooked_against_stored_oracle(n):
     assert sk.count(n, "hooked", no_shortcut=True) == want
 
 
+def test_small_instances_use_reference_body():
+    r = sk.count_ex(9, "skolem", no_shortcut=True)
+    assert r.count == 1328 and r.stats["kernel_variant"] == 1
+
+
 def test_invalid_arguments():
     with pytest.raises(sk.SkolemError):
         sk.count(0, "skolem")
@@ -147,3 +181,46 @@ def test_invalid_arguments():
         sk.partial_chunks(12, "skolem", 2, [4], PRIMES[:1])  # id >= 2^c
     with pytest.raises(sk.SkolemError):
         sk.sign_sum_residues(8, "skolem", [1000003])  # prime below the supported range
+
+
+MIXED = [(16, "skolem"), (17, "skolem"), (20, "skolem"), (21, "skolem"), (15, "langford"), (16, "langford"),
+         (19, "langford"), (20, "langford"), (14, "hooked"), (15, "hooked")]
+
+
+def _expected(n, variant):
+    if variant == "hooked":
+        return int(_load("oracle_counts.json")[f"hooked:{n}"]["ordered"])
+    return int(_load("paper_counts.json")[variant][str(n)])
+
+
+def test_batched_persistent_launch_mixed_instances():
+    """One persistent launch for Skolem 16, 17, 20, 21, Langford 15, 16, 19,
+    20 and hooked 14, 15 (printed values, Tables 7 and 8; hooked from the
+    oracle)."""
+    counts, st = sk.count_batch(MIXED, tuning={"log2_chunk_terms": 27, "waves_per_launch": 2048})
+    assert st["launches"] == 1 and st["kernel_variant"] == 3
+    for (n, v), c in zip(MIXED, counts):
+        assert c == _expected(n, v), (v, n, c)
+
+
+@pytest.mark.parametrize("lc,waves", [(24, 1024), (30, 4096)])
+def test_batched_launch_shape_does_not_change_result(lc, waves):
+    inst = [(16, "skolem"), (15, "langford"), (14, "hooked"), (17, "skolem")]
+    counts, _ = sk.count_batch(inst, tuning={"log2_chunk_terms": lc, "waves_per_launch": waves})
+    assert counts == [_expected(n, v) for n, v in inst]
+
+
+def test_batch_with_unbatched_instances_and_zeros():
+    inst = [(13, "skolem"), (12, "langford", sk.NO_SHORTCUT), (18, "skolem", sk.NO_SHORTCUT), (16, "skolem"),
+            (14, "hooked", sk.ORDERED), (10, "skolem"), (15, "hooked", sk.VERIFY)]
+    counts, st = sk.count_batch(inst)
+    want = [1520280, 108144, 0, 700078384, _expected(14, "hooked"), 0, _expected(15, "hooked")]
+    assert counts == want
+
+
+def test_autotune_returns_a_working_shape():
+    inst = [(16, "skolem"), (16, "langford"), (15, "hooked")]
+    best, rate = sk.autotune_batch(inst)
+    assert best["log2_chunk_terms"] >= 20 and best["waves_per_launch"] > 0 and rate > 0
+    counts, _ = sk.count_batch(inst)
+    assert counts == [_expected(n, v) for n, v in inst]

@@ -1,0 +1,81 @@
+"""GPU tempering (Sec. 3, Algorithm 2) against the CPU oracle.
+
+The chains use the same Philox4x32-10 streams and the same integer accept
+thresholds on both sides, so histograms, acceptance counts and final states
+must agree bit for bit (oracle schedule "even_odd").  The estimator is then
+checked statistically against exact counts.
+"""
+import math
+import sys
+
+import pytest
+
+import oracle as O
+import paper_1507_00315_amd as sk
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _ready():
+    O.build(force=False)
+    sk.lib()
+
+
+CASES = [("skolem", 5, [0.0, 0.3, 0.8, 1.5, 3.0, 6.0]),
+         ("skolem", 8, [0.0, 0.5, 1.0, 2.0, 4.0]),
+         ("langford", 7, [0.0, 0.4, 1.2, 2.5, 5.0, 9.0, 14.0]),
+         ("hooked", 7, [0.0, 0.7, 2.0, 4.0]),
+         ("skolem", 12, [0.0, 0.54, 1.1, 1.69, 2.33, 3, 3.73, 4.65, 5.82, 8.1, 16, 32])]
+
+
+@pytest.mark.parametrize("variant,n,betas", CASES)
+def test_chains_bit_exact_against_oracle(variant, n, betas):
+    ladders, iters, seed = 3, 4000, 777 + n
+    g = sk.pt_run(n, variant, betas, ladders, iters, seed)
+    for lad in range(ladders):
+        _say("pt parity", variant, n, "ladder", lad)
+        o = O.pt_ladder(n, variant, betas, iters, seed, ladder=lad, schedule="even_odd")
+        assert g["hist"][lad] == o["hist"]
+        assert g["move_accept"][lad] == o["move_accept"]
+        assert g["swap_accept"][lad][: len(betas) - 1] == o["swap_accept"][: len(betas) - 1]
+        assert g["state"][lad] == o["final_a"]
+        assert g["energy"][lad] == o["final_e"]
+
+
+def test_segments_carry_the_chains():
+    """Several kernel launches (segments) continue the same chains."""
+    betas = [0.0, 0.5, 1.5, 3.0, 6.0]
+    a = sk.pt_run(9, "skolem", betas, 2, 5000, 31, segment=777)
+    o = O.pt_ladder(9, "skolem", betas, 5000, 31, ladder=1, schedule="even_odd")
+    assert a["hist"][1] == o["hist"] and a["state"][1] == o["final_a"]
+
+
+def test_max_levels_and_size():
+    betas = [0.0] + [0.05 * (120 ** (j / 62)) for j in range(63)]
+    g = sk.pt_run(32, "skolem", betas, 1, 300, 5)
+    o = O.pt_ladder(32, "skolem", betas, 300, 5, ladder=0, schedule="even_odd")
+    assert g["hist"][0] == o["hist"] and g["state"][0] == o["final_a"]
+
+
+@pytest.mark.parametrize("variant,n", [("skolem", 8), ("langford", 8), ("hooked", 10)])
+def test_estimate_within_error_of_exact(variant, n):
+    betas = [0.0] + [0.25 * 1.45 ** i for i in range(12)]
+    est, se, st = sk.approx(n, variant, betas, ladders=64, iterations=1 << 15, seed=4242)
+    exact = O.reported(O.count_backtrack(n, variant, threads=8), n, variant)
+    _say(variant, n, est, se, exact)
+    assert abs(est - exact) < max(4 * se, 0.005 * exact)
+    assert 0 < st["move_accept"][0] <= 1 and st["gpu_ms"] > 0
+
+
+def test_invalid_ladders():
+    with pytest.raises(sk.SkolemError):
+        sk.approx(8, "skolem", [0.1, 0.5], 1, 10, 1)   # must start at beta = 0
+    with pytest.raises(sk.SkolemError):
+        sk.approx(8, "skolem", [0.0, 0.5, 0.4], 1, 10, 1)  # not ascending
+    with pytest.raises(sk.SkolemError):
+        sk.approx(1, "langford", [0.0, 1.0], 1, 10, 1)  # no configuration
