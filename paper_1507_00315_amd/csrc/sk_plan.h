@@ -104,7 +104,7 @@ __host__ __device__ constexpr PlanCE make_plan_ce(int n, int variant, int walk_c
             int tot = 0;
             for (int g = 0; g < G; ++g) tot += sizes[g];
             if (tot == P.nq) {
-                for (int heur = 0; heur < 2; ++heur) {
+                for (int heur = 0; heur < 4; ++heur) {
                     int cap[4] = {}, cnt[4] = {};
                     unsigned __int128 prod[4] = {1, 1, 1, 1};
                     int member[4][kMaxSlots] = {};
@@ -116,7 +116,27 @@ __host__ __device__ constexpr PlanCE make_plan_ce(int n, int variant, int walk_c
                     for (int i = 0; i < n && fits; ++i) {
                         const int k = order[i];
                         int best = -1;
-                        for (int g = 0; g < G; ++g) {
+                        if (heur == 2) {
+                            // largest factors first into the groups past the first two
+                            // (they only feed the 50-bit chain), then balance g0, g1
+                            for (int g = 2; g < G && best < 0; ++g)
+                                if (cnt[g] < cap[g] && prod[g] * u128_max1(fbound[k]) < two50) best = g;
+                            if (best < 0) {
+                                for (int g = 0; g < 2 && g < G; ++g) {
+                                    if (cnt[g] >= cap[g]) continue;
+                                    if (best < 0 || prod[g] < prod[best]) best = g;
+                                }
+                            }
+                        }
+                        if (heur == 3) {
+                            // fill the groups from the last one down, largest factors first
+                            for (int g = G - 1; g >= 0 && best < 0; --g) {
+                                if (cnt[g] >= cap[g]) continue;
+                                if (g >= 2 && prod[g] * u128_max1(fbound[k]) >= two50) continue;
+                                best = g;
+                            }
+                        }
+                        for (int g = 0; g < G && heur < 2; ++g) {
                             if (cnt[g] >= cap[g]) continue;
                             if (best < 0) {
                                 best = g;

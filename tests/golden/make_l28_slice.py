@@ -1,0 +1,63 @@
+"""Writes tests/golden/l28_slice_chunks.json: partial sums of 16 chunks of the
+Langford n = 28 sign-vector sum (Lemma 2.1), each over 2^31 sign vectors,
+recomputed on the CPU by the oracle's Gray-code walk modulo one prime.
+
+The 16 chunks are drawn (SplitMix64, seed 1508) from the 4096-chunk slice
+drawn with seed 1507 out of the 2^24 chunks; the chunk definition (which sign
+variables a chunk id fixes) is the one documented for sk_partial_chunks in
+include/skolem.h.  Calls only ``oracle`` and the seeded input module.
+
+    python tests/golden/make_l28_slice.py [threads]
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+import oracle as O  # noqa: E402
+from paper_1507_00315_amd import inputs  # noqa: E402  (seeded generators only)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT = os.path.join(HERE, "l28_slice_chunks.json")
+N, VARIANT, C = 28, "langford", 24
+
+
+def chunk_fixed(n, variant, c, cid):
+    pos, _ = O.instance(n, variant)
+    m = len(pos)
+    fixed = {pos[0]: 1}
+    for b in range(c):
+        rank = m - 6 - c + 1 + b
+        fixed[pos[rank - 1]] = -1 if (cid >> b) & 1 else 1
+    return fixed
+
+
+def main():
+    threads = int(sys.argv[1]) if len(sys.argv) > 1 else (os.cpu_count() or 1)
+    O.build(force=False)
+    slice_ids = inputs.distinct_ids(inputs.SLICE_SEED, C, 4096)
+    pick = inputs.subset(inputs.SLICE_SEED + 1, slice_ids, 16)
+    p = O.primes_below(1 << 46, 1)[0]
+    out = {"n": N, "variant": VARIANT, "log2_chunks": C, "slice_seed": inputs.SLICE_SEED,
+           "pick_seed": inputs.SLICE_SEED + 1, "prime": p, "chunks": []}
+    if os.path.exists(OUT):
+        with open(OUT) as f:
+            old = json.load(f)
+        if old.get("prime") == p:
+            out["chunks"] = old.get("chunks", [])
+    done = {c["id"] for c in out["chunks"]}
+    for cid in pick:
+        if cid in done:
+            continue
+        t0 = time.time()
+        r = O.chunk_partial(N, VARIANT, chunk_fixed(N, VARIANT, C, cid), p, "gray", threads=threads)
+        out["chunks"].append({"id": cid, "residue": r, "seconds": round(time.time() - t0, 1)})
+        print(cid, r, f"{time.time() - t0:.1f}s", flush=True)
+        with open(OUT, "w") as f:
+            json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
