@@ -208,6 +208,36 @@ sk_status sk_partial_chunks(int n, int variant, int log2_chunks, const uint64_t 
 #define SK_PROPOSAL_UNIFORM 0 /* pair uniform, placement uniform (Sec. 3) */
 #define SK_PROPOSAL_LEARNED 1 /* MLP proposal with Metropolis-Hastings correction */
 
+/*
+ * Learned proposal (not in the paper; an extension of Sec. 3's chains).  A
+ * network q(k, a' | C, beta) over single-pair moves is trained on states the
+ * chains generate and used as an extra Metropolis-Hastings move: each chain of
+ * levels first_level..M-1 proposes (k, a') ~ q(. | C) and accepts with
+ * min(1, exp(-beta (E(C') - E(C))) q(k, a_k | C') / q(k, a' | C)), so every
+ * level keeps exp(-beta E) as its stationary law.  The run:
+ *   1. train_iterations plain iterations (not recorded); the configurations
+ *      of the learned levels at `snapshots` evenly spaced points form the
+ *      training pool;
+ *   2. train_steps Adam steps (learning rate lr) on minibatches of the pool;
+ *   3. the recorded iterations, with one learned move of the learned levels
+ *      after every plain_per_learned plain iterations (network frozen).
+ * Learned moves use Philox counters (move index, 0xFFFFFFFE, ladder, level):
+ * word 0 picks the move, word 1 decides it.
+ */
+typedef struct {
+    int hidden1, hidden2;       /* hidden widths (0: 256) */
+    int first_level;            /* levels first_level..M-1 take learned moves */
+    uint64_t plain_per_learned; /* plain iterations per learned move, >= 1 */
+    uint64_t train_iterations;  /* plain iterations that feed the training pool */
+    int snapshots;              /* pool snapshots taken during them, >= 1 */
+    int train_steps;            /* Adam steps (0: use params as given) */
+    int minibatch;              /* states per Adam step */
+    double lr;                  /* Adam learning rate */
+    uint64_t init_seed;         /* initial weights when params is NULL */
+    float *params;              /* NULL, or sk_mlp_param_count floats: the initial
+                                   network in, the trained one out */
+} sk_learned_params;
+
 typedef struct {
     int levels;          /* M, 2..64 */
     const double *beta;  /* M ascending inverse temperatures, beta[0] == 0 */
@@ -217,6 +247,8 @@ typedef struct {
     int proposal;        /* SK_PROPOSAL_* */
     unsigned flags;      /* SK_ORDERED: estimate the ordered count */
     uint64_t segment;    /* iterations per kernel launch (0: 2^24); chains carry over */
+    uint64_t burn_in;    /* iterations run first and not recorded */
+    const sk_learned_params *learned; /* SK_PROPOSAL_LEARNED only */
 } sk_pt_params;
 
 typedef struct {
@@ -228,6 +260,11 @@ typedef struct {
     double wall_ms;
     uint64_t moves;         /* ladders x levels x iterations */
     int levels, ladders;
+    double learned_accept[64]; /* accepted learned moves that changed the configuration
+                                  / learned moves, per level */
+    uint64_t learned_moves;    /* learned moves per chain of a learned level */
+    double train_ms;           /* GPU time of the training phase (included in gpu_ms) */
+    double train_loss;         /* mean cross-entropy of the last Adam minibatch */
 } sk_pt_stats;
 
 /* Energy bins per level: 2n + 1 (Skolem, Langford) or 2n + 2 (hooked); -1 on
@@ -242,8 +279,11 @@ int sk_pt_bins(int n, int variant);
  *   state    : NULL or ladders x levels x n final placements a_k (1-based
  *              positions), in level order
  *   energy   : NULL or ladders x levels final energies
+ *   Burn-in and training iterations advance the chains but are not recorded;
+ *   their Philox counters precede the recorded ones (iteration numbers run
+ *   on from 0 across all phases).
  * Errors: SK_EINVAL (bad ladder: beta[0] != 0, not ascending, levels out of
- * range, no configuration), SK_ENOLIB (proposal not available), SK_EDEVICE.
+ * range, no configuration; bad learned parameters), SK_EDEVICE.
  */
 sk_status sk_pt_run(int n, int variant, const sk_pt_params *p, void *stream, uint64_t *hist,
                     uint64_t *move_acc, uint64_t *swap_acc, uint8_t *state, int32_t *energy);
@@ -256,6 +296,59 @@ sk_status sk_pt_run(int n, int variant, const sk_pt_params *p, void *stream, uin
  */
 sk_status sk_approx(int n, int variant, const sk_pt_params *p, void *stream, double *estimate,
                     double *std_error, sk_pt_stats *stats);
+
+/* ------------------------------------------------------------------------
+ * The proposal network (fp32, device-resident while a call runs).
+ *
+ * Input of configuration C at inverse temperature beta (din = T + 2n + 2
+ * values, T = largest position): occupancy indicator of each position 1..T,
+ * a_k / T for each pair, 1 if pair k shares a position with another pair,
+ * beta, E(C) / |P|.  Network: h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2),
+ * z = W3 h2 + b3 with dout = n * T logits, entry k * T + (a' - 1) for pair k
+ * at a'; q is the softmax over the valid placements.  Training target: the
+ * heat-bath law p*(k, a') proportional to exp(-beta E(C with a_k = a')),
+ * loss the mean cross-entropy -sum p* log q.
+ * Parameters: one flat fp32 array, row-major (out x in) weights,
+ *   W1[h1][din] b1[h1] W2[h2][h1] b2[h2] W3[dout][h2] b3[dout].
+ * states: batch x n placements a_k (1-based left positions, uint8), each a
+ * valid placement (else SK_EINVAL); betas: batch doubles (used as fp32).
+ * All buffers are host memory owned by the caller.  h1, h2 = 0 mean 256.
+ * ---------------------------------------------------------------------- */
+
+/* Number of parameters (0 on bad input). */
+size_t sk_mlp_param_count(int n, int variant, int h1, int h2);
+
+/* Gaussian initial weights (standard deviation scale / sqrt(fan in)), zero
+ * biases.  Host only. */
+sk_status sk_mlp_init(int n, int variant, int h1, int h2, uint64_t seed, double scale, float *params);
+
+/* logits: batch x (n * T) (entries of impossible placements are left as
+ * computed; q ignores them). */
+sk_status sk_mlp_forward(int n, int variant, int h1, int h2, const float *params, const uint8_t *states,
+                         const double *betas, int batch, void *stream, float *logits);
+
+/* Mean cross-entropy over the batch and its gradient (param layout). */
+sk_status sk_mlp_loss_grad(int n, int variant, int h1, int h2, const float *params, const uint8_t *states,
+                           const double *betas, int batch, void *stream, double *loss, float *grads);
+
+/* steps Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, moments from zero) on
+ * minibatches of the nstates states: step t uses rows (t * minibatch + i) mod
+ * nstates, i < minibatch.  params is updated in place; last_loss (nullable)
+ * receives the last minibatch's mean loss before its update. */
+sk_status sk_mlp_train(int n, int variant, int h1, int h2, float *params, const uint8_t *states,
+                       const double *betas, int nstates, int steps, int minibatch, double lr, void *stream,
+                       double *last_loss);
+
+/* One learned Metropolis-Hastings move per state.  The move (k, a') is the
+ * first entry j (in k * T + a' - 1 order over valid placements) whose
+ * cumulative q exceeds w_pick * 2^-32 times the total; it is accepted when
+ * w_acc * 2^-32 < min(1, exp(-beta dE) q(k, a_k | C') / q(k, a' | C)).
+ * out_states: resulting states; accepted, proposed (batch x n), logq_forward
+ * (log q(k, a' | C)) and logq_reverse (log q(k, a_k | C')) are nullable. */
+sk_status sk_mlp_mh_step(int n, int variant, int h1, int h2, const float *params, const uint8_t *states,
+                         const double *betas, const uint32_t *w_pick, const uint32_t *w_acc, int batch,
+                         void *stream, uint8_t *out_states, uint8_t *accepted, uint8_t *proposed,
+                         float *logq_forward, float *logq_reverse);
 
 /* Largest legal log2_chunks for sk_partial_chunks (negative on bad input). */
 int sk_max_chunk_bits(int n, int variant);

@@ -14,6 +14,8 @@ import os
 from dataclasses import dataclass
 from typing import Callable, Dict, Iterable, List, Optional, Sequence
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libskolem.so")
 
@@ -70,24 +72,35 @@ class PlanDesc(ctypes.Structure):
                 ("halved", ctypes.c_int), ("primes", ctypes.c_int), ("slot_factor", ctypes.c_int * 32)]
 
 
+class LearnedParams(ctypes.Structure):
+    _fields_ = [("hidden1", ctypes.c_int), ("hidden2", ctypes.c_int), ("first_level", ctypes.c_int),
+                ("plain_per_learned", ctypes.c_uint64), ("train_iterations", ctypes.c_uint64),
+                ("snapshots", ctypes.c_int), ("train_steps", ctypes.c_int), ("minibatch", ctypes.c_int),
+                ("lr", ctypes.c_double), ("init_seed", ctypes.c_uint64), ("params", ctypes.POINTER(ctypes.c_float))]
+
+
 class PtParams(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("beta", ctypes.POINTER(ctypes.c_double)), ("ladders", ctypes.c_int),
                 ("iterations", ctypes.c_uint64), ("seed", ctypes.c_uint64), ("proposal", ctypes.c_int),
-                ("flags", ctypes.c_uint), ("segment", ctypes.c_uint64)]
+                ("flags", ctypes.c_uint), ("segment", ctypes.c_uint64), ("burn_in", ctypes.c_uint64),
+                ("learned", ctypes.POINTER(LearnedParams))]
 
 
 class PtStats(ctypes.Structure):
     _fields_ = [("mean_energy", ctypes.c_double * 64), ("move_accept", ctypes.c_double * 64),
                 ("swap_accept", ctypes.c_double * 64), ("ratio", ctypes.c_double * 64),
                 ("gpu_ms", ctypes.c_double), ("wall_ms", ctypes.c_double), ("moves", ctypes.c_uint64),
-                ("levels", ctypes.c_int), ("ladders", ctypes.c_int)]
+                ("levels", ctypes.c_int), ("ladders", ctypes.c_int), ("learned_accept", ctypes.c_double * 64),
+                ("learned_moves", ctypes.c_uint64), ("train_ms", ctypes.c_double), ("train_loss", ctypes.c_double)]
 
     def as_dict(self) -> Dict:
         M = self.levels
         return {"mean_energy": list(self.mean_energy[:M]), "move_accept": list(self.move_accept[:M]),
                 "swap_accept": list(self.swap_accept[:M]), "ratio": list(self.ratio[:M]),
                 "gpu_ms": self.gpu_ms, "wall_ms": self.wall_ms, "moves": int(self.moves),
-                "levels": M, "ladders": self.ladders}
+                "levels": M, "ladders": self.ladders, "learned_accept": list(self.learned_accept[:M]),
+                "learned_moves": int(self.learned_moves), "train_ms": self.train_ms,
+                "train_loss": self.train_loss}
 
 
 PROGRESS_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64)
@@ -124,6 +137,19 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(U128)]
     L.sk_autotune_batch.argtypes = [ctypes.POINTER(Instance), c_size, vp, ctypes.POINTER(Tuning),
                                     ctypes.POINTER(ctypes.c_double)]
+    fp = ctypes.POINTER(ctypes.c_float)
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.sk_mlp_param_count.argtypes = [c_int, c_int, c_int, c_int]
+    L.sk_mlp_param_count.restype = c_size
+    L.sk_mlp_init.argtypes = [c_int, c_int, c_int, c_int, ctypes.c_uint64, ctypes.c_double, fp]
+    L.sk_mlp_forward.argtypes = [c_int, c_int, c_int, c_int, fp, u8p, dp, c_int, vp, fp]
+    L.sk_mlp_loss_grad.argtypes = [c_int, c_int, c_int, c_int, fp, u8p, dp, c_int, vp, dp, fp]
+    L.sk_mlp_train.argtypes = [c_int, c_int, c_int, c_int, fp, u8p, dp, c_int, c_int, c_int, ctypes.c_double, vp,
+                               dp]
+    L.sk_mlp_mh_step.argtypes = [c_int, c_int, c_int, c_int, fp, u8p, dp, u32p, u32p, c_int, vp, u8p, u8p, u8p, fp,
+                                 fp]
     L.sk_strerror.argtypes = [c_int]
     L.sk_strerror.restype = ctypes.c_char_p
     L.sk_last_error.restype = ctypes.c_char_p
@@ -131,7 +157,8 @@ def lib() -> ctypes.CDLL:
     L.sk_kernel_name.restype = ctypes.c_char_p
     for fn in ("sk_set_device", "sk_count", "sk_count_ex", "sk_sign_sum_residues", "sk_partial_chunks",
                "sk_max_chunk_bits", "sk_describe", "sk_count_batch", "sk_autotune_batch", "sk_pt_bins",
-               "sk_pt_run", "sk_approx"):
+               "sk_pt_run", "sk_approx", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
+               "sk_mlp_mh_step"):
         getattr(L, fn).restype = c_int
     _lib = L
     return L
@@ -139,7 +166,9 @@ def lib() -> ctypes.CDLL:
 
 EXPORTED = ["sk_set_device", "sk_count", "sk_count_ex", "sk_count_batch", "sk_autotune_batch", "sk_pt_bins",
             "sk_pt_run", "sk_approx", "sk_sign_sum_residues", "sk_partial_chunks",
-            "sk_max_chunk_bits", "sk_describe", "sk_strerror", "sk_last_error", "sk_u128_to_decimal", "sk_kernel_name"]
+            "sk_max_chunk_bits", "sk_describe", "sk_strerror", "sk_last_error", "sk_u128_to_decimal", "sk_kernel_name",
+            "sk_mlp_param_count", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
+            "sk_mlp_mh_step"]
 
 
 def _variant(v) -> int:
@@ -288,11 +317,32 @@ def describe(n: int, variant) -> Dict:
 PROPOSAL_UNIFORM, PROPOSAL_LEARNED = 0, 1
 
 
-def _pt_params(betas, ladders, iterations, seed, proposal, ordered, segment):
+def _learned_params(learned: Optional[Dict]):
+    """sk_learned_params from a dict (keys as in the C struct); params, if
+    given, is a float32 numpy array that receives the trained network."""
+    if learned is None:
+        return None, None
+    params = learned.get("params")
+    ptr = None
+    if params is not None:
+        if not (isinstance(params, np.ndarray) and params.dtype == np.float32 and params.flags.c_contiguous):
+            raise TypeError("learned['params'] must be a contiguous float32 numpy array")
+        ptr = params.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    lp = LearnedParams(int(learned.get("hidden1", 0)), int(learned.get("hidden2", 0)),
+                       int(learned.get("first_level", 0)), int(learned.get("plain_per_learned", 1)),
+                       int(learned.get("train_iterations", 0)), int(learned.get("snapshots", 1)),
+                       int(learned.get("train_steps", 0)), int(learned.get("minibatch", 256)),
+                       float(learned.get("lr", 1e-3)), int(learned.get("init_seed", 0)), ptr)
+    return lp, params
+
+
+def _pt_params(betas, ladders, iterations, seed, proposal, ordered, segment, burn_in=0, learned=None):
     arr = (ctypes.c_double * len(betas))(*[float(x) for x in betas])
+    lp, params = _learned_params(learned)
     p = PtParams(len(betas), arr, int(ladders), int(iterations), int(seed), int(proposal),
-                 ORDERED if ordered else 0, int(segment))
-    return p, arr
+                 ORDERED if ordered else 0, int(segment), int(burn_in),
+                 ctypes.pointer(lp) if lp is not None else None)
+    return p, (arr, lp, params)
 
 
 def pt_bins(n: int, variant) -> int:
@@ -300,14 +350,15 @@ def pt_bins(n: int, variant) -> int:
 
 
 def pt_run(n: int, variant, betas: Sequence[float], ladders: int, iterations: int, seed: int,
-           proposal: int = PROPOSAL_UNIFORM, segment: int = 0, stream=None) -> Dict:
+           proposal: int = PROPOSAL_UNIFORM, segment: int = 0, stream=None, burn_in: int = 0,
+           learned: Optional[Dict] = None) -> Dict:
     """Runs the tempering ladders (Sec. 3) and returns raw chain statistics:
     hist[ladder][level][E], move/exchange acceptance counts, final states."""
     M = len(betas)
     H = pt_bins(n, variant)
     if H < 0:
         raise SkolemError(-1, "sk_pt_bins")
-    p, keep = _pt_params(betas, ladders, iterations, seed, proposal, False, segment)
+    p, keep = _pt_params(betas, ladders, iterations, seed, proposal, False, segment, burn_in, learned)
     hist = (ctypes.c_uint64 * (ladders * M * H))()
     ma = (ctypes.c_uint64 * (ladders * M))()
     sw = (ctypes.c_uint64 * (ladders * M))()
@@ -323,15 +374,106 @@ def pt_run(n: int, variant, betas: Sequence[float], ladders: int, iterations: in
 
 
 def approx(n: int, variant, betas: Sequence[float], ladders: int, iterations: int, seed: int,
-           proposal: int = PROPOSAL_UNIFORM, ordered: bool = False, segment: int = 0, stream=None):
-    """Approximate count by parallel tempering: (estimate, standard error, stats)."""
-    p, keep = _pt_params(betas, ladders, iterations, seed, proposal, ordered, segment)
+           proposal: int = PROPOSAL_UNIFORM, ordered: bool = False, segment: int = 0, stream=None,
+           burn_in: int = 0, learned: Optional[Dict] = None):
+    """Approximate count by parallel tempering: (estimate, standard error, stats).
+    With proposal=PROPOSAL_LEARNED, ``learned`` holds the sk_learned_params
+    fields (see include/skolem.h)."""
+    p, keep = _pt_params(betas, ladders, iterations, seed, proposal, ordered, segment, burn_in, learned)
     est = ctypes.c_double()
     se = ctypes.c_double()
     st = PtStats()
     _check(lib().sk_approx(n, _variant(variant), ctypes.byref(p), _stream_handle(stream), ctypes.byref(est),
                            ctypes.byref(se), ctypes.byref(st)), "sk_approx")
     return est.value, se.value, st.as_dict()
+
+
+# ---------------------------------------------------------------- network
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _states(states, n: int) -> np.ndarray:
+    s = np.ascontiguousarray(states, dtype=np.uint8)
+    if s.ndim != 2 or s.shape[1] != n:
+        raise ValueError(f"states must be (batch, {n})")
+    return s
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def mlp_param_count(n: int, variant, h1: int = 0, h2: int = 0) -> int:
+    return int(lib().sk_mlp_param_count(n, _variant(variant), h1, h2))
+
+
+def mlp_init(n: int, variant, h1: int = 0, h2: int = 0, seed: int = 0, scale: float = 1.0) -> np.ndarray:
+    P = np.zeros(mlp_param_count(n, variant, h1, h2), dtype=np.float32)
+    _check(lib().sk_mlp_init(n, _variant(variant), h1, h2, seed, scale, _ptr(P, ctypes.c_float)), "sk_mlp_init")
+    return P
+
+
+def mlp_forward(n: int, variant, params, states, betas, h1: int = 0, h2: int = 0, stream=None) -> np.ndarray:
+    """Logits (batch, n * T) of the proposal network on the GPU."""
+    P, S = _f32(params), _states(states, n)
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    B = S.shape[0]
+    T = pt_bins(n, variant) - 1
+    out = np.zeros((B, n * T), dtype=np.float32)
+    _check(lib().sk_mlp_forward(n, _variant(variant), h1, h2, _ptr(P, ctypes.c_float), _ptr(S, ctypes.c_uint8),
+                                _ptr(b, ctypes.c_double), B, _stream_handle(stream), _ptr(out, ctypes.c_float)),
+           "sk_mlp_forward")
+    return out
+
+
+def mlp_loss_grad(n: int, variant, params, states, betas, h1: int = 0, h2: int = 0, stream=None):
+    """(mean cross-entropy, gradient in parameter layout) on the GPU."""
+    P, S = _f32(params), _states(states, n)
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    g = np.zeros_like(P)
+    loss = ctypes.c_double()
+    _check(lib().sk_mlp_loss_grad(n, _variant(variant), h1, h2, _ptr(P, ctypes.c_float), _ptr(S, ctypes.c_uint8),
+                                  _ptr(b, ctypes.c_double), S.shape[0], _stream_handle(stream), ctypes.byref(loss),
+                                  _ptr(g, ctypes.c_float)), "sk_mlp_loss_grad")
+    return loss.value, g
+
+
+def mlp_train(n: int, variant, params, states, betas, steps: int, minibatch: int, lr: float, h1: int = 0,
+              h2: int = 0, stream=None):
+    """Adam on the GPU; returns (trained params, last minibatch loss)."""
+    P, S = _f32(params).copy(), _states(states, n)
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    loss = ctypes.c_double()
+    _check(lib().sk_mlp_train(n, _variant(variant), h1, h2, _ptr(P, ctypes.c_float), _ptr(S, ctypes.c_uint8),
+                              _ptr(b, ctypes.c_double), S.shape[0], steps, minibatch, lr, _stream_handle(stream),
+                              ctypes.byref(loss)), "sk_mlp_train")
+    return P, loss.value
+
+
+def mlp_mh_step(n: int, variant, params, states, betas, w_pick, w_acc, h1: int = 0, h2: int = 0,
+                stream=None) -> Dict:
+    """One learned Metropolis-Hastings move per state on the GPU."""
+    P, S = _f32(params), _states(states, n)
+    B = S.shape[0]
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    wp = np.ascontiguousarray(w_pick, dtype=np.uint32)
+    wa = np.ascontiguousarray(w_acc, dtype=np.uint32)
+    if b.shape != (B,) or wp.shape != (B,) or wa.shape != (B,):
+        raise ValueError("betas, w_pick and w_acc need one entry per state")
+    out = np.zeros_like(S)
+    acc = np.zeros(B, dtype=np.uint8)
+    prop = np.zeros_like(S)
+    lf = np.zeros(B, dtype=np.float32)
+    lr = np.zeros(B, dtype=np.float32)
+    _check(lib().sk_mlp_mh_step(n, _variant(variant), h1, h2, _ptr(P, ctypes.c_float), _ptr(S, ctypes.c_uint8),
+                                _ptr(b, ctypes.c_double), _ptr(wp, ctypes.c_uint32), _ptr(wa, ctypes.c_uint32), B,
+                                _stream_handle(stream), _ptr(out, ctypes.c_uint8), _ptr(acc, ctypes.c_uint8),
+                                _ptr(prop, ctypes.c_uint8), _ptr(lf, ctypes.c_float), _ptr(lr, ctypes.c_float)),
+           "sk_mlp_mh_step")
+    return {"states": out, "accepted": acc.astype(bool), "proposed": prop, "logq_forward": lf, "logq_reverse": lr}
 
 
 def kernel_name(kv: int) -> str:
@@ -342,5 +484,7 @@ def last_stats_dict(st: Stats) -> Dict:
     return st.as_dict()
 
 
-__all__ = ["count", "count_ex", "count_batch", "autotune_batch", "pt_run", "approx", "pt_bins", "sign_sum_residues", "partial_chunks", "max_chunk_bits", "set_device",
+__all__ = ["count", "count_ex", "count_batch", "autotune_batch", "pt_run", "approx", "pt_bins", "sign_sum_residues",
+           "partial_chunks", "max_chunk_bits", "set_device", "mlp_param_count", "mlp_init", "mlp_forward",
+           "mlp_loss_grad", "mlp_train", "mlp_mh_step", "PROPOSAL_UNIFORM", "PROPOSAL_LEARNED",
            "SkolemError", "SKOLEM", "LANGFORD", "HOOKED", "lib", "EXPORTED"]

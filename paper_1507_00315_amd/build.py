@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libskolem.so")
 
-SOURCES = ["host.cpp", "pt_host.cpp", "exact_v1.hip", "exact_batch.hip", "pt.hip"]
+SOURCES = ["host.cpp", "pt_host.cpp", "mlp_host.cpp", "exact_v1.hip", "exact_batch.hip", "pt.hip", "mlp.hip"]
 
 # Tuned kernel specialisations: (variant, n_min, n_max) per translation unit,
 # so they compile in parallel.

@@ -10,6 +10,8 @@
 #include <vector>
 
 #include "../../include/skolem.h"
+#include "sk_mlp.h"
+#include "sk_mlp_net.h"
 #include "sk_pt.h"
 
 namespace sk {
@@ -58,104 +60,265 @@ static bool relaxed_of(int n, int variant, Relaxed& R)
         hipError_t e_ = (call);                                                       \
         if (e_ != hipSuccess) {                                                       \
             set_last_error(std::string(#call) + ": " + hipGetErrorString(e_));        \
-            status = SK_EDEVICE;                                                      \
-            goto done;                                                                \
+            return SK_EDEVICE;                                                        \
         }                                                                             \
     } while (0)
 
-// Runs every ladder for p->iterations iterations; outputs are filled (not added).
+#define PT_OK(expr)                             \
+    do {                                        \
+        sk_status s_ = (expr);                  \
+        if (s_ != SK_OK) return s_;             \
+    } while (0)
+
+// What a run reports besides the recorded statistics.
+struct PtExtra {
+    double gpu_ms = 0, train_ms = 0, train_loss = 0;
+    uint64_t learned_moves = 0;
+    std::vector<uint64_t> learned_acc;  // ladders x levels
+};
+
+// Device state of one run: thresholds, the two configuration buffers the
+// segments alternate between, and the recorded statistics.
+struct PtDevice {
+    uint32_t *mt = nullptr, *st = nullptr;
+    uint8_t *sa = nullptr, *sb = nullptr;
+    int32_t* e = nullptr;
+    uint64_t *h = nullptr, *ma = nullptr, *sw = nullptr, *la = nullptr;
+    float* beta_f = nullptr;
+    uint8_t *pool = nullptr;
+    float* pool_beta = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    uint8_t* cur = nullptr;  // configurations after the last segment (nullptr: fresh start)
+    ~PtDevice()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        for (void* p : {(void*)mt, (void*)st, (void*)sa, (void*)sb, (void*)e, (void*)h, (void*)ma, (void*)sw,
+                        (void*)la, (void*)beta_f, (void*)pool, (void*)pool_beta})
+            if (p) (void)hipFree(p);
+    }
+};
+
+// Enqueues plain iterations [it0, it1) in launches of at most seg iterations.
+// An empty range still launches once if refresh is set or no configuration
+// exists yet: that launch draws (or copies) the configurations and writes
+// their energies.
+static sk_status enqueue_plain(PtDevice& D, PtArgs a, int ladders, size_t lds, uint64_t seg, uint64_t it0,
+                               uint64_t it1, hipStream_t stream, bool refresh = false)
+{
+    if (it0 == it1 && D.cur && !refresh) return SK_OK;
+    for (uint64_t it = it0; it < it1 || it == it0; it += seg) {
+        a.it_begin = it;
+        a.it_end = std::min<uint64_t>(it1, it + seg);
+        a.state_in = D.cur;
+        a.state_out = (D.cur == D.sa) ? D.sb : D.sa;
+        for (int base = 0; base < ladders; base += 65535) {
+            a.ladder_base = (uint32_t)base;
+            const unsigned cnt = (unsigned)std::min(65535, ladders - base);
+            PT_HIP(launch_pt_ladders(cnt, lds, stream, a));
+        }
+        D.cur = a.state_out;
+    }
+    return SK_OK;
+}
+
+static sk_status clear_stats(PtDevice& D, size_t nh, size_t nl, hipStream_t stream)
+{
+    PT_HIP(hipMemsetAsync(D.h, 0, nh * sizeof(uint64_t), stream));
+    PT_HIP(hipMemsetAsync(D.ma, 0, nl * sizeof(uint64_t), stream));
+    PT_HIP(hipMemsetAsync(D.sw, 0, nl * sizeof(uint64_t), stream));
+    if (D.la) PT_HIP(hipMemsetAsync(D.la, 0, nl * sizeof(uint64_t), stream));
+    return SK_OK;
+}
+
+static sk_status elapsed(PtDevice& D, hipStream_t stream, double& ms_out)
+{
+    PT_HIP(hipEventRecord(D.e1, stream));
+    PT_HIP(hipEventSynchronize(D.e1));
+    float ms = 0.f;
+    PT_HIP(hipEventElapsedTime(&ms, D.e0, D.e1));
+    ms_out += ms;
+    return SK_OK;
+}
+
+// Chains per learned batch (the network's activations are sized for it).
+constexpr long kLearnBatch = 65536;
+
+// One learned move of every chain of levels j0..M-1, in batches.
+static sk_status learned_move(MlpNet& net, PtDevice& D, int n, int M, int j0, long chains, uint64_t seed,
+                              uint32_t step, hipStream_t stream)
+{
+    const int nsel = M - j0;
+    for (long base = 0; base < chains; base += kLearnBatch) {
+        const int B = (int)std::min<long>(kLearnBatch, chains - base);
+        PT_HIP(launch_gather(n, D.cur, M, j0, nsel, base, D.beta_f, B, net.s_sel, net.betaf, stream));
+        PT_HIP(launch_words(seed, step, j0, nsel, base, B, net.w_pick, net.w_acc, stream));
+        PT_OK(net.mh_step(B, M, j0, nsel, base, D.cur, D.la, nullptr, stream));
+    }
+    return SK_OK;
+}
+
+// Runs burn-in (and for the learned proposal, the training phase), then
+// p->iterations recorded iterations; outputs are filled (not added).
 static sk_status pt_run_impl(const Relaxed& R, const sk_pt_params* p, hipStream_t stream, uint64_t* hist,
-                             uint64_t* move_acc, uint64_t* swap_acc, uint8_t* state, int32_t* energy, double* gpu_ms)
+                             uint64_t* move_acc, uint64_t* swap_acc, uint8_t* state, int32_t* energy, PtExtra* ex)
 {
     const int M = p->levels, Lad = p->ladders, H = R.top + 1, n = R.n;
-    sk_status status = SK_OK;
-    std::vector<uint32_t> mt(2 * M), st((size_t)M * H, 0);
+    const bool learned = p->proposal == SK_PROPOSAL_LEARNED;
+    std::vector<uint32_t> mt(2 * M), stt((size_t)M * H, 0);
     for (int j = 0; j < M; ++j) {
         mt[2 * j] = accept_threshold(p->beta[j], 1);
         mt[2 * j + 1] = accept_threshold(p->beta[j], 2);
         if (j + 1 < M)
-            for (int e = 1; e < H; ++e) st[(size_t)j * H + e] = accept_threshold(p->beta[j + 1] - p->beta[j], e);
+            for (int e = 1; e < H; ++e) stt[(size_t)j * H + e] = accept_threshold(p->beta[j + 1] - p->beta[j], e);
     }
-    uint32_t *d_mt = nullptr, *d_st = nullptr;
-    uint8_t *d_sa = nullptr, *d_sb = nullptr;
-    int32_t* d_e = nullptr;
-    uint64_t *d_h = nullptr, *d_ma = nullptr, *d_sw = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PtDevice D;
     const size_t nst = (size_t)Lad * M * n, nh = (size_t)Lad * M * H, nl = (size_t)Lad * M;
     const int slot_bytes = (n + H + 3) & ~3;
     const size_t lds = (size_t)64 * slot_bytes + (size_t)M * H * sizeof(uint32_t);
     // iterations per launch; LDS counters stay below 2^32
     const uint64_t seg = (p->segment > 0 && p->segment <= (1ull << 30)) ? p->segment : (1ull << 24);
-    float total_ms = 0.f;
-    PT_HIP(hipMalloc(&d_mt, mt.size() * sizeof(uint32_t)));
-    PT_HIP(hipMalloc(&d_st, st.size() * sizeof(uint32_t)));
-    PT_HIP(hipMalloc(&d_sa, nst));
-    PT_HIP(hipMalloc(&d_sb, nst));
-    PT_HIP(hipMalloc(&d_e, nl * sizeof(int32_t)));
-    PT_HIP(hipMalloc(&d_h, nh * sizeof(uint64_t)));
-    PT_HIP(hipMalloc(&d_ma, nl * sizeof(uint64_t)));
-    PT_HIP(hipMalloc(&d_sw, nl * sizeof(uint64_t)));
-    PT_HIP(hipEventCreate(&e0));
-    PT_HIP(hipEventCreate(&e1));
-    PT_HIP(hipMemcpyAsync(d_mt, mt.data(), mt.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
-    PT_HIP(hipMemcpyAsync(d_st, st.data(), st.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
-    PT_HIP(hipMemsetAsync(d_h, 0, nh * sizeof(uint64_t), stream));
-    PT_HIP(hipMemsetAsync(d_ma, 0, nl * sizeof(uint64_t), stream));
-    PT_HIP(hipMemsetAsync(d_sw, 0, nl * sizeof(uint64_t), stream));
-    {
-        PtArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.n = n;
-        a.variant = R.variant;
-        a.top = R.top;
-        a.levels = M;
-        a.pset = R.pset;
-        a.slot_bytes = slot_bytes;
-        a.seed = p->seed;
-        a.move_thr = d_mt;
-        a.swap_thr = d_st;
-        a.energy_out = d_e;
-        a.hist_out = d_h;
-        a.move_acc = d_ma;
-        a.swap_acc = d_sw;
-        uint8_t* cur_in = nullptr;
-        uint8_t* cur_out = d_sa;
-        for (uint64_t it = 0; it < p->iterations || it == 0; it += seg) {
-            a.it_begin = it;
-            a.it_end = std::min<uint64_t>(p->iterations, it + seg);
-            a.state_in = cur_in;
-            a.state_out = cur_out;
-            // ladders in groups of at most 65535 blocks
-            PT_HIP(hipEventRecord(e0, stream));
-            for (int base = 0; base < Lad; base += 65535) {
-                a.ladder_base = (uint32_t)base;
-                const unsigned cnt = (unsigned)std::min(65535, Lad - base);
-                PT_HIP(launch_pt_ladders(cnt, lds, stream, a));
-            }
-            PT_HIP(hipEventRecord(e1, stream));
-            PT_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            PT_HIP(hipEventElapsedTime(&ms, e0, e1));
-            total_ms += ms;
-            cur_in = cur_out;
-            cur_out = (cur_out == d_sa) ? d_sb : d_sa;
-            if (p->iterations == 0) break;
-        }
-        PT_HIP(hipMemcpyAsync(hist, d_h, nh * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
-        PT_HIP(hipMemcpyAsync(move_acc, d_ma, nl * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
-        PT_HIP(hipMemcpyAsync(swap_acc, d_sw, nl * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
-        if (state) PT_HIP(hipMemcpyAsync(state, cur_in, nst, hipMemcpyDeviceToHost, stream));
-        if (energy) PT_HIP(hipMemcpyAsync(energy, d_e, nl * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-        PT_HIP(hipStreamSynchronize(stream));
+    PT_HIP(hipMalloc(&D.mt, mt.size() * sizeof(uint32_t)));
+    PT_HIP(hipMalloc(&D.st, stt.size() * sizeof(uint32_t)));
+    PT_HIP(hipMalloc(&D.sa, nst));
+    PT_HIP(hipMalloc(&D.sb, nst));
+    PT_HIP(hipMalloc(&D.e, nl * sizeof(int32_t)));
+    PT_HIP(hipMalloc(&D.h, nh * sizeof(uint64_t)));
+    PT_HIP(hipMalloc(&D.ma, nl * sizeof(uint64_t)));
+    PT_HIP(hipMalloc(&D.sw, nl * sizeof(uint64_t)));
+    PT_HIP(hipEventCreate(&D.e0));
+    PT_HIP(hipEventCreate(&D.e1));
+    PT_HIP(hipMemcpyAsync(D.mt, mt.data(), mt.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
+    PT_HIP(hipMemcpyAsync(D.st, stt.data(), stt.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
+
+    PtArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = n;
+    a.variant = R.variant;
+    a.top = R.top;
+    a.levels = M;
+    a.pset = R.pset;
+    a.slot_bytes = slot_bytes;
+    a.seed = p->seed;
+    a.move_thr = D.mt;
+    a.swap_thr = D.st;
+    a.energy_out = D.e;
+    a.hist_out = D.h;
+    a.move_acc = D.ma;
+    a.swap_acc = D.sw;
+
+    double gpu_ms = 0, train_ms = 0, train_loss = 0;
+    uint64_t it = 0;  // iteration counter across all phases (Philox counters)
+    uint64_t learned_moves = 0;
+    MlpNet net;
+    const sk_learned_params* L = p->learned;
+    const int j0 = learned ? L->first_level : 0;
+    const long chains = (long)Lad * (M - j0);
+
+    PT_HIP(hipEventRecord(D.e0, stream));
+    PT_OK(clear_stats(D, nh, nl, stream));
+    if (p->burn_in > 0) {
+        PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it + p->burn_in, stream));
+        it += p->burn_in;
     }
-    if (gpu_ms) *gpu_ms = total_ms;
-done:
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    for (void* ptr : {(void*)d_mt, (void*)d_st, (void*)d_sa, (void*)d_sb, (void*)d_e, (void*)d_h, (void*)d_ma,
-                      (void*)d_sw})
-        if (ptr) (void)hipFree(ptr);
-    return status;
+    if (learned) {
+        MlpGeo g;
+        if (!mlp_geometry(n, R.variant, g)) return SK_EINVAL;
+        PT_OK(net.init(g, L->hidden1, L->hidden2));
+        if (L->params) {
+            PT_HIP(hipMemcpyAsync(net.P, L->params, net.count * sizeof(float), hipMemcpyHostToDevice, stream));
+        } else {
+            std::vector<float> init(net.count);
+            PT_OK(sk_mlp_init(n, R.variant, L->hidden1, L->hidden2, L->init_seed, 1.0, init.data()));
+            PT_HIP(hipMemcpyAsync(net.P, init.data(), net.count * sizeof(float), hipMemcpyHostToDevice, stream));
+            PT_HIP(hipStreamSynchronize(stream));
+        }
+        std::vector<float> bf(p->beta, p->beta + M);
+        PT_HIP(hipMalloc(&D.beta_f, M * sizeof(float)));
+        PT_HIP(hipMalloc(&D.la, nl * sizeof(uint64_t)));
+        PT_HIP(hipMemcpyAsync(D.beta_f, bf.data(), M * sizeof(float), hipMemcpyHostToDevice, stream));
+        PT_HIP(hipMemsetAsync(D.la, 0, nl * sizeof(uint64_t), stream));
+        if (L->train_steps > 0) {
+            // training pool: the learned levels' configurations at each snapshot
+            const int S = L->snapshots;
+            const long N = chains * S;
+            PT_HIP(hipMalloc(&D.pool, (size_t)N * n));
+            PT_HIP(hipMalloc(&D.pool_beta, (size_t)N * sizeof(float)));
+            for (int snap = 0; snap < S; ++snap) {
+                const uint64_t len = L->train_iterations / S + (snap + 1 == S ? L->train_iterations % S : 0);
+                PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it + len, stream));
+                it += len;
+                PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it, stream));
+                for (long base = 0; base < chains; base += kLearnBatch) {
+                    const int B = (int)std::min<long>(kLearnBatch, chains - base);
+                    PT_HIP(launch_gather(n, D.cur, M, j0, M - j0, base, D.beta_f, B,
+                                         D.pool + ((size_t)snap * chains + base) * n,
+                                         D.pool_beta + (size_t)snap * chains + base, stream));
+                }
+            }
+            double before = 0;
+            PT_OK(elapsed(D, stream, before));
+            PT_HIP(hipEventRecord(D.e0, stream));
+            PT_OK(net.reserve((int)std::min<long>(L->minibatch, kLearnBatch)));
+            PT_OK(net.train_pool(D.pool, D.pool_beta, (int)N, L->train_steps,
+                                 (int)std::min<long>(L->minibatch, kLearnBatch), (float)L->lr, stream, &train_loss));
+            PT_OK(elapsed(D, stream, train_ms));
+            gpu_ms += before + train_ms;
+            PT_HIP(hipEventRecord(D.e0, stream));
+            net.free_batch();
+            PT_HIP(hipFree(D.pool));
+            PT_HIP(hipFree(D.pool_beta));
+            D.pool = nullptr;
+            D.pool_beta = nullptr;
+        } else if (L->train_iterations > 0) {
+            PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it + L->train_iterations, stream));
+            it += L->train_iterations;
+        }
+        PT_OK(net.reserve((int)std::min<long>(chains, kLearnBatch)));
+        PT_OK(clear_stats(D, nh, nl, stream));
+        PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it, stream));
+        // recorded phase: plain blocks, each followed by a learned move
+        const uint64_t blk = L->plain_per_learned;
+        uint64_t done = 0;
+        while (done < p->iterations) {
+            const uint64_t len = std::min<uint64_t>(blk, p->iterations - done);
+            PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it + len, stream));
+            it += len;
+            done += len;
+            if (len == blk) {
+                PT_OK(learned_move(net, D, n, M, j0, chains, p->seed, (uint32_t)learned_moves, stream));
+                ++learned_moves;
+            }
+        }
+        // energies of the configurations the last learned move left
+        if (learned_moves > 0) PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it, stream, true));
+    } else {
+        PT_OK(clear_stats(D, nh, nl, stream));
+        PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it + p->iterations, stream));
+        it += p->iterations;
+    }
+    PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it, stream));  // zero iterations: initial states
+    PT_OK(elapsed(D, stream, gpu_ms));
+
+    PT_HIP(hipMemcpyAsync(hist, D.h, nh * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+    PT_HIP(hipMemcpyAsync(move_acc, D.ma, nl * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+    PT_HIP(hipMemcpyAsync(swap_acc, D.sw, nl * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+    if (state) PT_HIP(hipMemcpyAsync(state, D.cur, nst, hipMemcpyDeviceToHost, stream));
+    if (energy) PT_HIP(hipMemcpyAsync(energy, D.e, nl * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    if (ex && D.la) {
+        ex->learned_acc.resize(nl);
+        PT_HIP(hipMemcpyAsync(ex->learned_acc.data(), D.la, nl * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+    }
+    PT_HIP(hipStreamSynchronize(stream));
+    if (ex) {
+        ex->gpu_ms = gpu_ms;
+        ex->train_ms = train_ms;
+        ex->train_loss = train_loss;
+        ex->learned_moves = learned_moves;
+    }
+    if (learned && L->params && L->train_steps > 0)
+        PT_HIP(hipMemcpy(L->params, net.P, net.count * sizeof(float), hipMemcpyDeviceToHost));
+    return SK_OK;
 }
 
 static sk_status check_params(const Relaxed& R, const sk_pt_params* p)
@@ -166,7 +329,17 @@ static sk_status check_params(const Relaxed& R, const sk_pt_params* p)
         if (!(p->beta[j] > p->beta[j - 1]) || !std::isfinite(p->beta[j])) return SK_EINVAL;
     for (int x : R.L)
         if (x == 0) return SK_EINVAL;  // no configuration at all
-    if (p->proposal != SK_PROPOSAL_UNIFORM) return SK_ENOLIB;
+    if (p->proposal == SK_PROPOSAL_UNIFORM) return SK_OK;
+    if (p->proposal != SK_PROPOSAL_LEARNED) return SK_EINVAL;
+    const sk_learned_params* L = p->learned;
+    if (!L || L->first_level < 0 || L->first_level >= p->levels || L->plain_per_learned < 1 || L->hidden1 < 0 ||
+        L->hidden2 < 0 || L->hidden1 > 4096 || L->hidden2 > 4096)
+        return SK_EINVAL;
+    if (L->train_steps < 0) return SK_EINVAL;
+    if (L->train_steps > 0 &&
+        (L->snapshots < 1 || L->minibatch < 1 || !(L->lr > 0) || L->train_iterations < (uint64_t)L->snapshots))
+        return SK_EINVAL;
+    if (L->train_steps == 0 && !L->params) return SK_EINVAL;  // an untrained fresh network is of no use
     return SK_OK;
 }
 
@@ -219,8 +392,8 @@ sk_status sk_approx(int n, int variant, const sk_pt_params* p, void* stream, dou
         if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) return SK_EDEVICE;
         st = own;
     }
-    double ms = 0;
-    s = pt_run_impl(R, p, st, hist.data(), ma.data(), sw.data(), nullptr, nullptr, &ms);
+    PtExtra ex;
+    s = pt_run_impl(R, p, st, hist.data(), ma.data(), sw.data(), nullptr, nullptr, &ex);
     if (own) (void)hipStreamDestroy(own);
     if (s != SK_OK) return s;
 
@@ -263,7 +436,10 @@ sk_status sk_approx(int n, int variant, const sk_pt_params* p, void* stream, dou
         std::memset(stats, 0, sizeof(*stats));
         stats->levels = M;
         stats->ladders = Lad;
-        stats->gpu_ms = ms;
+        stats->gpu_ms = ex.gpu_ms;
+        stats->train_ms = ex.train_ms;
+        stats->train_loss = ex.train_loss;
+        stats->learned_moves = ex.learned_moves;
         stats->moves = (uint64_t)Lad * M * p->iterations;
         for (int j = 0; j < M; ++j) {
             double tot = 0, se_sum = 0, num = 0, acc = 0, swa = 0;
@@ -284,6 +460,11 @@ sk_status sk_approx(int n, int variant, const sk_pt_params* p, void* stream, dou
             // exchanges of (j, j+1) are attempted on every other iteration
             const double tries = (double)Lad * (double)((p->iterations + ((j & 1) ? 0 : 1)) / 2);
             stats->swap_accept[j] = (j + 1 < M && tries > 0) ? swa / tries : 0;
+            if (!ex.learned_acc.empty() && ex.learned_moves > 0) {
+                double la = 0;
+                for (int l = 0; l < Lad; ++l) la += (double)ex.learned_acc[(size_t)l * M + j];
+                stats->learned_accept[j] = la / ((double)Lad * (double)ex.learned_moves);
+            }
         }
         stats->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }

@@ -23,7 +23,7 @@ def test_library_present_and_exports_every_declared_symbol():
     assert "sk_count" in names and "sk_partial_chunks" in names
     for name in names:
         assert hasattr(L, name), name
-    assert set(names) <= set(sk.EXPORTED) | {"sk_approx"} or True
+    assert set(names) <= set(sk.EXPORTED), sorted(set(names) - set(sk.EXPORTED))
 
 
 def test_strerror_and_decimal_are_host_only():
@@ -57,3 +57,16 @@ def test_no_gpu_reports_device_error_not_fallback():
     with pytest.raises(sk.SkolemError) as ei:
         sk.count(8, "skolem")
     assert ei.value.status in (-3,)
+
+
+def test_network_size_and_init_are_host_only():
+    # 130 -> 256 -> 256 -> 32 x 64 for Skolem n = 32
+    assert sk.mlp_param_count(32, "skolem") == 130 * 256 + 256 + 256 * 256 + 256 + 2048 * 256 + 2048 == 625664
+    assert sk.mlp_param_count(31, "hooked", 16, 8) == (63 + 62 + 2) * 16 + 16 + 16 * 8 + 8 + 31 * 63 * 8 + 31 * 63
+    assert sk.mlp_param_count(33, "skolem") == 0
+    a = sk.mlp_init(32, "skolem", seed=4)
+    b = sk.mlp_init(32, "skolem", seed=4)
+    assert (a == b).all() and not (a == sk.mlp_init(32, "skolem", seed=5)).all()
+    W1 = a[:256 * 130]
+    assert abs(W1.std() * (130 ** 0.5) - 1.0) < 0.02 and abs(W1.mean()) < 0.01
+    assert (a[256 * 130:256 * 131] == 0).all()  # b1

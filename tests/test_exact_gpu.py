@@ -224,3 +224,18 @@ def test_autotune_returns_a_working_shape():
     assert best["log2_chunk_terms"] >= 20 and best["waves_per_launch"] > 0 and rate > 0
     counts, _ = sk.count_batch(inst)
     assert counts == [_expected(n, v) for n, v in inst]
+
+
+def test_l28_slice_chunks_match_cpu_recomputation():
+    """Langford n = 28 at its full size (2^24 chunks of 2^31 sign vectors): the
+    16 chunks of the 4096-chunk slice recomputed on the CPU by the oracle
+    (tests/golden/l28_slice_chunks.json, written by make_l28_slice.py) must
+    match bit for bit, in the launch the slice benchmark times."""
+    with open(os.path.join(GOLD, "l28_slice_chunks.json")) as f:
+        g = json.load(f)
+    assert len(g["chunks"]) == 16
+    ids = [c["id"] for c in g["chunks"]]
+    assert set(ids) <= set(inputs.distinct_ids(g["slice_seed"], g["log2_chunks"], 4096))
+    _say("l28 slice: 16 chunks of 2^31 terms")
+    rows = sk.partial_chunks(g["n"], g["variant"], g["log2_chunks"], ids, [g["prime"]])
+    assert [r[0] for r in rows] == [c["residue"] for c in g["chunks"]]

@@ -1,0 +1,253 @@
+"""GPU proposal network against the float64 CPU oracle (oracle/mlp.py).
+
+The network runs in fp32 (MFMA GEMMs, wave-level softmax); the oracle in
+fp64.  Forward logits, loss and gradients are compared with tolerances derived
+from fp32 rounding over the contraction lengths used here (relative error of a
+length-K fp32 dot product is at most about K * 2^-24; K <= 2048 here, and the
+observed errors sit far below the bounds).  Integer decisions (which move is
+proposed, whether it is accepted) are compared where the oracle's fp64 margin
+exceeds the fp32 error; the rest are checked for validity.  Exactness in
+distribution of the Metropolis-Hastings move is checked against the exact
+Boltzmann law of a small instance, enumerated on the host.
+"""
+import itertools
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp as OM
+import paper_1507_00315_amd as sk
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _ready():
+    O.build(force=False)
+    sk.lib()
+
+
+def unpack(g: OM.Geometry, P: np.ndarray, h1: int, h2: int):
+    """Flat fp32 parameters (W1 b1 W2 b2 W3 b3, row-major) -> oracle dict (fp64)."""
+    P = P.astype(np.float64)
+    out, o = {}, 0
+    for name, shape in (("W1", (h1, g.din)), ("b1", (h1,)), ("W2", (h2, h1)), ("b2", (h2,)),
+                        ("W3", (g.dout, h2)), ("b3", (g.dout,))):
+        size = int(np.prod(shape))
+        out[name] = P[o:o + size].reshape(shape)
+        o += size
+    assert o == P.size
+    return out
+
+
+def pack(d) -> np.ndarray:
+    return np.concatenate([d[k].reshape(-1) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]).astype(np.float32)
+
+
+def random_states(g: OM.Geometry, B: int, rng) -> np.ndarray:
+    S = np.zeros((B, g.n), dtype=np.uint8)
+    for k in range(g.n):
+        choices = np.nonzero(g.valid[k])[0] + 1
+        S[:, k] = rng.choice(choices, size=B)
+    return S
+
+
+SHAPES = [  # (variant, n, h1, h2, batch): ragged tiles in every GEMM dimension
+    ("skolem", 6, 80, 48, 100),
+    ("langford", 7, 64, 72, 37),
+    ("hooked", 5, 33, 65, 129),
+    ("skolem", 32, 256, 256, 70),   # the full-size network (130 -> 256 -> 256 -> 2048)
+]
+
+
+@pytest.mark.parametrize("variant,n,h1,h2,B", SHAPES)
+def test_forward_matches_oracle(variant, n, h1, h2, B):
+    _say("mlp forward", variant, n, h1, h2, B)
+    g = OM.Geometry(n, variant)
+    rng = np.random.default_rng(11 + n)
+    P = sk.mlp_init(n, variant, h1, h2, seed=3, scale=1.5)
+    S = random_states(g, B, rng)
+    betas = rng.uniform(0, 6, size=B)
+    z = sk.mlp_forward(n, variant, P, S, betas, h1, h2)
+    X = np.stack([OM.features(g, list(S[i]), betas[i]) for i in range(B)])
+    zo, _ = OM.forward(unpack(g, P, h1, h2), X)
+    scale = np.abs(zo).max()
+    err = np.abs(z - zo).max()
+    _say("  max |dz| =", err, "max |z| =", scale)
+    assert err <= 2e-5 * max(scale, 1.0) * math.sqrt(max(h1, h2, g.din))
+
+
+@pytest.mark.parametrize("variant,n,h1,h2,B", SHAPES)
+def test_loss_and_gradient_match_oracle(variant, n, h1, h2, B):
+    _say("mlp grad", variant, n, h1, h2, B)
+    g = OM.Geometry(n, variant)
+    rng = np.random.default_rng(21 + n)
+    P = sk.mlp_init(n, variant, h1, h2, seed=5, scale=1.0)
+    S = random_states(g, B, rng)
+    betas = rng.uniform(0, 4, size=B)
+    loss, grad = sk.mlp_loss_grad(n, variant, P, S, betas, h1, h2)
+    lo, go = OM.loss_and_grad(unpack(g, P, h1, h2), g, [list(s) for s in S], list(betas))
+    _say("  loss", loss, lo)
+    assert abs(loss - lo) <= 1e-5 * max(1.0, abs(lo)) * 10
+    gg = unpack(g, grad, h1, h2)
+    for k in go:
+        ref = go[k]
+        rel = np.linalg.norm(gg[k] - ref) / max(np.linalg.norm(ref), 1e-12)
+        _say("  grad", k, "relative error", rel)
+        assert rel < 2e-4, k
+
+
+def test_adam_training_matches_oracle():
+    n, variant, h1, h2 = 6, "skolem", 48, 40
+    g = OM.Geometry(n, variant)
+    rng = np.random.default_rng(7)
+    P0 = sk.mlp_init(n, variant, h1, h2, seed=9)
+    N, B, steps, lr = 45, 16, 4, 1e-3
+    S = random_states(g, N, rng)
+    betas = rng.uniform(0, 3, size=N)
+    P1, last = sk.mlp_train(n, variant, P0, S, betas, steps, B, lr, h1, h2)
+    # oracle: the same cyclic minibatches
+    Pd = unpack(g, P0, h1, h2)
+    M = {k: np.zeros_like(v) for k, v in Pd.items()}
+    V = {k: np.zeros_like(v) for k, v in Pd.items()}
+    lo = None
+    for t in range(steps):
+        rows = [(t * B + i) % N for i in range(B)]
+        lo, G = OM.loss_and_grad(Pd, g, [list(S[r]) for r in rows], [betas[r] for r in rows])
+        OM.adam(Pd, G, M, V, t + 1, lr=lr)
+    ref = pack(Pd)
+    d = np.abs(P1.astype(np.float64) - ref.astype(np.float64))
+    moved = np.abs(ref.astype(np.float64) - P0.astype(np.float64))
+    _say("adam: loss", last, lo, "median diff", np.median(d), "max diff", d.max(), "median move", np.median(moved))
+    assert abs(last - lo) < 1e-4 * max(1.0, abs(lo))
+    # Adam moves each weight by about lr per step; fp32 vs fp64 may flip the
+    # sign of a near-zero gradient, so compare the bulk, and bound the rest
+    assert np.median(d) < 1e-3 * lr
+    assert np.mean(d > 0.1 * lr) < 0.01
+    assert d.max() <= 2 * lr * steps + 1e-6
+
+
+def _oracle_decision(Pd, g, a, beta, wp, wa):
+    """The oracle's proposal index, margins, log q's and decision."""
+    mask = g.valid.reshape(-1)
+    z, _ = OM.forward(Pd, OM.features(g, a, beta)[None, :])
+    lq = OM.masked_log_softmax(z, mask[None, :])[0]
+    q = np.where(mask, np.exp(lq), 0.0)
+    cdf = np.cumsum(q)
+    u = wp * 2.0 ** -32
+    j = int(np.searchsorted(cdf, u * cdf[-1], side="right"))
+    j = min(j, g.dout - 1)
+    while not mask[j]:
+        j -= 1
+    margin = min(abs(u * cdf[-1] - cdf[j]), abs(u * cdf[-1] - (cdf[j - 1] if j > 0 else 0.0)))
+    return j, margin, lq
+
+
+@pytest.mark.parametrize("variant,n,h1,h2", [("skolem", 6, 64, 64), ("skolem", 32, 256, 256),
+                                            ("hooked", 6, 40, 40)])
+def test_mh_step_matches_oracle(variant, n, h1, h2):
+    _say("mh step", variant, n)
+    g = OM.Geometry(n, variant)
+    rng = np.random.default_rng(31 + n)
+    B = 200
+    P = sk.mlp_init(n, variant, h1, h2, seed=13, scale=2.0)
+    Pd = unpack(g, P, h1, h2)
+    S = random_states(g, B, rng)
+    betas = rng.uniform(0, 3, size=B)
+    wp = rng.integers(0, 2 ** 32, size=B, dtype=np.uint64).astype(np.uint32)
+    wa = rng.integers(0, 2 ** 32, size=B, dtype=np.uint64).astype(np.uint32)
+    r = sk.mlp_mh_step(n, variant, P, S, betas, wp, wa, h1, h2)
+    compared = 0
+    for i in range(B):
+        a = list(S[i])
+        prop = list(r["proposed"][i])
+        diff = [k for k in range(n) if prop[k] != a[k]]
+        assert len(diff) <= 1
+        jo, margin, lq = _oracle_decision(Pd, g, a, betas[i], int(wp[i]), int(wa[i]))
+        if diff:
+            k = diff[0]
+            jg = k * g.T + prop[k] - 1
+        else:  # the proposal re-placed some pair where it already was
+            jg = None
+        assert all(g.valid[k, prop[k] - 1] for k in range(n))
+        if margin > 1e-4:
+            if jg is not None:
+                assert jg == jo, (i, jg, jo)
+            else:
+                ko, apo = divmod(jo, g.T)
+                assert a[ko] == apo + 1
+            assert abs(r["logq_forward"][i] - lq[jo]) < 2e-4 * max(1.0, abs(lq[jo]))
+            ko, apo = divmod(jo, g.T)
+            b = list(a)
+            old = b[ko]
+            b[ko] = apo + 1
+            zb, _ = OM.forward(Pd, OM.features(g, b, betas[i])[None, :])
+            lqb = OM.masked_log_softmax(zb, g.valid.reshape(-1)[None, :])[0]
+            lrev = lqb[ko * g.T + old - 1]
+            assert abs(r["logq_reverse"][i] - lrev) < 2e-4 * max(1.0, abs(lrev))
+            log_alpha = -betas[i] * (g.energy(b) - g.energy(a)) + lrev - lq[jo]
+            u = int(wa[i]) * 2.0 ** -32
+            if u > 0 and abs(math.log(u) - min(0.0, log_alpha)) > 1e-3:
+                acc = math.log(u) < min(0.0, log_alpha)
+                assert bool(r["accepted"][i]) == acc, i
+                assert list(r["states"][i]) == (b if acc else a)
+                compared += 1
+    _say("  decisions compared:", compared, "of", B)
+    assert compared > 0.9 * B
+
+
+def _boltzmann_table(g: OM.Geometry, beta: float):
+    """All configurations of a small instance, their energies and exact law."""
+    choices = [list(np.nonzero(g.valid[k])[0] + 1) for k in range(g.n)]
+    confs = np.array(list(itertools.product(*choices)), dtype=np.uint8)
+    E = np.array([g.energy(list(c)) for c in confs])
+    w = np.exp(-beta * (E - E.min()))
+    return confs, E, w / w.sum()
+
+
+@pytest.mark.parametrize("beta", [0.0, 1.0, 2.5])
+def test_mh_step_keeps_boltzmann_law(beta):
+    """Start from exact samples of exp(-beta E) and apply learned moves with a
+    deliberately skewed (random, large-weight) network: the law of the energy
+    must not move.  A missing or inverted Hastings factor skews it."""
+    n, variant, h1, h2 = 4, "skolem", 32, 32
+    g = OM.Geometry(n, variant)
+    confs, E, p = _boltzmann_table(g, beta)
+    rng = np.random.default_rng(1000 + int(10 * beta))
+    B, steps = 20000, 6
+    S = confs[rng.choice(len(confs), size=B, p=p)]
+    P = sk.mlp_init(n, variant, h1, h2, seed=77, scale=4.0)
+    betas = np.full(B, beta)
+    acc = 0
+    for _ in range(steps):
+        wp = rng.integers(0, 2 ** 32, size=B, dtype=np.uint64).astype(np.uint32)
+        wa = rng.integers(0, 2 ** 32, size=B, dtype=np.uint64).astype(np.uint32)
+        r = sk.mlp_mh_step(n, variant, P, S, betas, wp, wa, h1, h2)
+        S = r["states"]
+        acc += int(r["accepted"].sum())
+    Ef = np.array([g.energy(list(s)) for s in S])
+    Hmax = E.max() + 1
+    expect = np.array([p[E == e].sum() for e in range(Hmax)]) * B
+    got = np.bincount(Ef, minlength=Hmax)[:Hmax]
+    keep = expect > 5
+    chi2 = float(((got[keep] - expect[keep]) ** 2 / expect[keep]).sum())
+    dof = int(keep.sum()) - 1
+    _say("beta", beta, "acceptance", acc / (B * steps), "chi2", chi2, "dof", dof, got, np.round(expect))
+    assert acc > 0.05 * B * steps
+    # chi-square with dof <= 8: P(chi2 > 30) < 3e-4
+    assert chi2 < 30
+
+
+def test_invalid_inputs():
+    P = sk.mlp_init(4, "skolem", 8, 8)
+    with pytest.raises(sk.SkolemError):
+        sk.mlp_forward(4, "skolem", P, np.array([[1, 1, 1, 9]], dtype=np.uint8), [0.5], 8, 8)  # 9 + 4 > 8
+    with pytest.raises(sk.SkolemError):
+        sk.mlp_forward(4, "skolem", P, np.array([[0, 1, 1, 1]], dtype=np.uint8), [0.5], 8, 8)  # position 0
