@@ -14,6 +14,9 @@ Workloads (all inputs are the problem statements themselves: no data files):
   l24    Langford n = 24
   s20    Skolem n = 20;  l20  Langford n = 20
   s12    Skolem n = 12, two primes (the small correctness case)
+  l28slice  Langford n = 28: a seeded 1/4096 subset of its 2^24 prefix chunks
+         (2^43 sign vectors) with the three primes a full count needs; the
+         projected full-count time is reported
 """
 from __future__ import annotations
 
@@ -37,7 +40,9 @@ WORKLOADS = {
     "s20": [("skolem", 20)],
     "l20": [("langford", 20)],
     "s12": [("skolem", 12)],
+    "l28slice": [("langford", 28)],
 }
+L28_CHUNK_BITS, L28_SLICE = 24, 4096
 
 
 def log(*a):
@@ -100,6 +105,48 @@ def cpu_baseline(instances, threads):
                       f"{dt:.1f} s"}
 
 
+def config5_ladder():
+    """48 levels: beta = 0 (the relaxed problem's exact normaliser) and 47
+    geometric steps from 0.05 to 6."""
+    return [0.0] + [0.05 * (6.0 / 0.05) ** (j / 46) for j in range(47)]
+
+
+def pt_bench(sk, want, iters: int, ladders: int, learned_cfg: dict, seed: int = 1507):
+    """Tempering estimates (Sec. 3) on the 48-level ladder: relative error
+    against the printed S(20), S(24) and GPU seconds, plain uniform moves and
+    the learned proposal; S(32) beside the paper's own estimate.  Each run
+    burns in (and, learned, trains on) iters / 4 iterations first."""
+    betas = config5_ladder()
+    runs = []
+    for n in (20, 24, 32):
+        exact = want.get(("skolem", n))
+        for name in ("plain", "learned"):
+            kw = dict(ladders=ladders, iterations=iters, seed=seed + n, burn_in=0 if name == "learned" else iters // 4)
+            if name == "learned":
+                kw["proposal"] = sk.PROPOSAL_LEARNED
+                kw["learned"] = dict(learned_cfg, train_iterations=iters // 4)
+            t0 = time.time()
+            est, se, st = sk.approx(n, "skolem", betas, **kw)
+            rec = {"n": n, "proposal": name, "estimate": est, "std_error": se, "rel_std_error": se / est if est else None,
+                   "gpu_s": st["gpu_ms"] * 1e-3, "train_gpu_s": st["train_ms"] * 1e-3, "wall_s": time.time() - t0,
+                   "iterations": iters, "ladders": ladders}
+            if exact:
+                rec["exact"] = exact
+                rec["rel_error"] = abs(est - exact) / exact
+            if name == "learned":
+                rec["learned_moves"] = st["learned_moves"]
+                rec["learned_accept_top"] = st["learned_accept"][-1]
+                rec["learned_accept_mean"] = sum(st["learned_accept"][learned_cfg["first_level"]:]) / (
+                    len(betas) - learned_cfg["first_level"])
+                rec["train_loss"] = st["train_loss"]
+            rec["plain_move_accept_top"] = st["move_accept"][-1]
+            log(f"pt {name} S({n}): {est:.6g} +- {se:.3g}" + (f" (exact {exact}, rel err {rec['rel_error']:.2e})"
+                                                               if exact else "") + f"  gpu {rec['gpu_s']:.2f} s")
+            runs.append(rec)
+    return {"ladder": "beta_0 = 0, then 47 geometric levels 0.05 .. 6", "levels": len(betas), "runs": runs,
+            "paper_S32_estimate": 2.2e26}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +158,11 @@ def main():
     ap.add_argument("--kernel", type=int, default=0)
     ap.add_argument("--separate", action="store_true", help="batch workload as one launch per instance")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-pt", action="store_true", help="skip the tempering estimates")
+    ap.add_argument("--pt-iters", type=int, default=1 << 14)
+    ap.add_argument("--pt-ladders", type=int, default=1024)
+    ap.add_argument("--pt-learned-every", type=int, default=64)
+    ap.add_argument("--pt-learned-first", type=int, default=24)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -130,8 +182,23 @@ def main():
         tuning["primes"] = 2
     want = expected_values()
 
+    slice_ids = None
+    if args.workload == "l28slice":
+        from paper_1507_00315_amd import inputs
+        slice_ids = inputs.distinct_ids(inputs.SLICE_SEED, L28_CHUNK_BITS, L28_SLICE)
+        slice_primes = sk.describe(28, "langford")["primes"]  # default primes, as a full count uses
+
     def step(tag):
         res = []
+        if slice_ids is not None:
+            t0 = time.time()
+            rows, st = sk.partial_chunks(28, "langford", L28_CHUNK_BITS, slice_ids, slice_primes,
+                                         tuning=tuning if args.log2_chunk or args.kernel else None,
+                                         with_stats=True)
+            res.append(("langford", 28, None, st, None))
+            log(f"[{tag}] l28 slice: {len(rows)} chunks, kernel {st['kernel_ms']:.1f} ms "
+                f"{st['terms'] / max(st['kernel_ms'], 1e-9) * 1e3:.3e} terms/s  wall {time.time() - t0:.1f} s")
+            return res
         if args.workload == "batch" and not args.separate:
             counts, st = sk.count_batch([(n, v, sk.ORDERED if v == "hooked" else 0) for v, n in instances],
                                         tuning=tuning if args.log2_chunk else None)
@@ -189,7 +256,8 @@ def main():
         d = sk.describe(n, v)
         d["primes_used"] = d["primes"]
         instr_per = valu_per_term(d)
-        terms_inst = 1 << (2 * n - 1)
+        # sign vectors the kernel evaluates (half of 2^(2n-1) where Lemma 2.4 applies)
+        terms_inst = terms_per_step if slice_ids is not None else (1 << (2 * n - 1)) >> d["symmetric"]
         instr += terms_inst * instr_per
     kms = sum(s["kernel_ms"] for st in results for s in stats_of(st)) / args.steps
     launches = sum(s["launches"] for st in results for s in stats_of(st)) // args.steps
@@ -215,12 +283,26 @@ def main():
                    "terms_per_step": terms_per_step,
                    "primes_per_instance": {f"{v}:{n}": sk.describe(n, v)["primes"] for v, n in instances},
                    "log2_chunk_terms": stats_of(results[0])[0]["log2_chunk_terms"],
+                   "lemma_2_4_halving": bool(stats_of(results[0])[0].get("symmetry_halved")),
+                   "sign_vectors_covered_per_step": (terms_per_step if slice_ids is not None else
+                                                     sum(1 << (2 * n - 1) for v, n in instances)),
                    "results_match_expected": all_ok},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "VALU lane-instr/s",
                      "frac": achieved / PEAK_LANE_OPS, "traffic": None, "kernel": kernel_name,
                      "valu_instr_per_term": instr_per_term, "terms_per_s_kernel": terms_per_step / (kms * 1e-3),
                      "launches": launches, "avg_launch_ms": kms / max(launches, 1)},
     }
+    if slice_ids is not None:
+        full_chunks = 1 << L28_CHUNK_BITS
+        line["config"]["slice"] = {"chunks": len(slice_ids), "of_chunks": full_chunks,
+                                   "terms_per_chunk": terms_per_step // len(slice_ids), "seed": 1507,
+                                   "projected_full_count_s": kms * 1e-3 * full_chunks / len(slice_ids),
+                                   "projected_full_count_wall_s": elapsed / args.steps * full_chunks / len(slice_ids)}
+    if args.workload == "batch" and not args.no_pt:
+        learned_cfg = dict(hidden1=256, hidden2=256, first_level=args.pt_learned_first,
+                           plain_per_learned=args.pt_learned_every, snapshots=8, train_steps=400, minibatch=1024,
+                           lr=1e-3, init_seed=1)
+        line["pt"] = pt_bench(sk, want, args.pt_iters, args.pt_ladders, learned_cfg)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log("cpu baseline ...")

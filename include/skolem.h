@@ -60,6 +60,12 @@ typedef enum {
 #define SK_VERIFY      0x4u /* run the whole sum a second time modulo a disjoint set of
                                primes and require both results to agree (the analogue of
                                the paper's duplicate GPU jobs, Sec. 1.3) */
+#define SK_NO_SYMMETRY 0x8u /* evaluate every sign vector with x_1 = +1.  By default, when
+                               the term is invariant under negating the even positions
+                               (Lemma 2.4; for every variant this holds exactly when the
+                               existence conditions do), only the half with the highest
+                               chunk variable (an even position) at +1 is evaluated and
+                               the sum is doubled */
 
 /* Unsigned 128-bit integer; every count with n <= 32 fits. */
 typedef struct { uint64_t lo, hi; } sk_u128;
@@ -84,14 +90,15 @@ typedef struct {
 typedef struct {
     int n;
     int variant;     /* sk_variant */
-    unsigned flags;  /* SK_ORDERED | SK_NO_SHORTCUT | SK_VERIFY */
+    unsigned flags;  /* SK_ORDERED | SK_NO_SHORTCUT | SK_VERIFY | SK_NO_SYMMETRY */
 } sk_instance;
 
 /* Timing and shape of the last completed call on this thread. */
 typedef struct {
     double kernel_ms;        /* sum of kernel durations (HIP events on the launch stream) */
     double wall_ms;          /* whole call, host clock */
-    uint64_t terms;          /* sign vectors evaluated (x_1 fixed) */
+    uint64_t terms;          /* sign vectors evaluated (x_1 fixed; half of them when
+                                symmetry_halved) */
     uint64_t launches;       /* kernel launches */
     uint64_t chunks;         /* wavefront work units */
     int nprimes;             /* primes used per pass */
@@ -100,6 +107,7 @@ typedef struct {
     int kernel_variant;      /* which kernel body ran (see sk_kernel_name) */
     double ms_per_launch_avg;
     uint64_t primes[8];
+    int symmetry_halved;     /* 1 if the Lemma 2.4 half was evaluated and doubled */
 } sk_stats;
 
 /* Progress callback: return nonzero to abort (the call then returns SK_EABORTED). */
@@ -178,7 +186,8 @@ sk_status sk_sign_sum_residues(int n, int variant, const uint64_t *primes, int n
  *   log2_chunks : c, 0 <= c <= 2n - 7 - (the count of low variables the
  *                 kernel walks; sk_max_chunk_bits gives the largest legal c)
  *   chunk_ids   : nchunks ids, each < 2^c (repeats allowed)
- *   primes      : nprimes (1..8) primes with 2^45 < p < 2^46
+ *   primes      : nprimes (1..8) primes with 2^45 < p < 2^46, or NULL for the
+ *                 nprimes largest primes below 2^46 (the ones sk_count uses)
  *   tune        : waves_per_launch and kernel fields are used (NULL: defaults)
  *   residues_out: nchunks x nprimes, row-major, each the chunk's signed sum
  *                 of (prod x) prod_k f_k(x) modulo the prime, in [0, p)
@@ -187,6 +196,10 @@ sk_status sk_sign_sum_residues(int n, int variant, const uint64_t *primes, int n
 sk_status sk_partial_chunks(int n, int variant, int log2_chunks, const uint64_t *chunk_ids,
                             size_t nchunks, const uint64_t *primes, int nprimes,
                             const sk_tuning *tune, void *stream, uint64_t *residues_out);
+
+/* Totals of the last sk_count, sk_count_ex, sk_count_batch,
+ * sk_sign_sum_residues or sk_partial_chunks call made by this thread. */
+sk_status sk_last_stats(sk_stats *out);
 
 
 /* ------------------------------------------------------------------------
@@ -364,6 +377,8 @@ typedef struct {
     int halved;       /* factors with an even number of pairs, stored as f_k / 2 */
     int primes;       /* primes per pass chosen by sk_count */
     int slot_factor[32]; /* factor index k-1 in each slot, -1 for a constant-1 slot */
+    int symmetric;    /* 1 if the term is invariant under negating the even positions
+                         (Lemma 2.4), so sk_count evaluates half the sign vectors */
 } sk_plan_desc;
 
 sk_status sk_describe(int n, int variant, sk_plan_desc *out);

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libskolem.so")
 SKOLEM, LANGFORD, HOOKED = 0, 1, 2
 VARIANTS = {"skolem": SKOLEM, "langford": LANGFORD, "hooked": HOOKED}
 
-ORDERED, NO_SHORTCUT, VERIFY = 0x1, 0x2, 0x4
+ORDERED, NO_SHORTCUT, VERIFY, NO_SYMMETRY = 0x1, 0x2, 0x4, 0x8
 
 STATUS = {0: "SK_OK", -1: "SK_EINVAL", -2: "SK_ERANGE", -3: "SK_EDEVICE", -4: "SK_ECHECK",
           -5: "SK_ENOMEM", -6: "SK_EABORTED", -7: "SK_ENOLIB"}
@@ -54,7 +54,8 @@ class Stats(ctypes.Structure):
                 ("terms", ctypes.c_uint64), ("launches", ctypes.c_uint64),
                 ("chunks", ctypes.c_uint64), ("nprimes", ctypes.c_int), ("passes", ctypes.c_int),
                 ("log2_chunk_terms", ctypes.c_int), ("kernel_variant", ctypes.c_int),
-                ("ms_per_launch_avg", ctypes.c_double), ("primes", ctypes.c_uint64 * 8)]
+                ("ms_per_launch_avg", ctypes.c_double), ("primes", ctypes.c_uint64 * 8),
+                ("symmetry_halved", ctypes.c_int)]
 
     def as_dict(self) -> Dict:
         d = {name: getattr(self, name) for name, _ in self._fields_ if name != "primes"}
@@ -69,7 +70,8 @@ class Instance(ctypes.Structure):
 class PlanDesc(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("n_lane", ctypes.c_int), ("n_walk", ctypes.c_int),
                 ("n_job", ctypes.c_int), ("quads", ctypes.c_int), ("groups", ctypes.c_int),
-                ("halved", ctypes.c_int), ("primes", ctypes.c_int), ("slot_factor", ctypes.c_int * 32)]
+                ("halved", ctypes.c_int), ("primes", ctypes.c_int), ("slot_factor", ctypes.c_int * 32),
+                ("symmetric", ctypes.c_int)]
 
 
 class LearnedParams(ctypes.Structure):
@@ -127,6 +129,7 @@ def lib() -> ctypes.CDLL:
     L.sk_partial_chunks.argtypes = [c_int, c_int, c_int, u64p, c_size, u64p, c_int, ctypes.POINTER(Tuning), vp,
                                     u64p]
     L.sk_max_chunk_bits.argtypes = [c_int, c_int]
+    L.sk_last_stats.argtypes = [ctypes.POINTER(Stats)]
     L.sk_describe.argtypes = [c_int, c_int, ctypes.POINTER(PlanDesc)]
     L.sk_pt_bins.argtypes = [c_int, c_int]
     L.sk_pt_run.argtypes = [c_int, c_int, ctypes.POINTER(PtParams), vp, u64p, u64p, u64p,
@@ -157,7 +160,7 @@ def lib() -> ctypes.CDLL:
     L.sk_kernel_name.restype = ctypes.c_char_p
     for fn in ("sk_set_device", "sk_count", "sk_count_ex", "sk_sign_sum_residues", "sk_partial_chunks",
                "sk_max_chunk_bits", "sk_describe", "sk_count_batch", "sk_autotune_batch", "sk_pt_bins",
-               "sk_pt_run", "sk_approx", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
+               "sk_pt_run", "sk_approx", "sk_last_stats", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
                "sk_mlp_mh_step"):
         getattr(L, fn).restype = c_int
     _lib = L
@@ -167,7 +170,7 @@ def lib() -> ctypes.CDLL:
 EXPORTED = ["sk_set_device", "sk_count", "sk_count_ex", "sk_count_batch", "sk_autotune_batch", "sk_pt_bins",
             "sk_pt_run", "sk_approx", "sk_sign_sum_residues", "sk_partial_chunks",
             "sk_max_chunk_bits", "sk_describe", "sk_strerror", "sk_last_error", "sk_u128_to_decimal", "sk_kernel_name",
-            "sk_mlp_param_count", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
+            "sk_last_stats", "sk_mlp_param_count", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
             "sk_mlp_mh_step"]
 
 
@@ -208,11 +211,17 @@ class CountResult:
     stats: Dict
 
 
+def _flags(ordered, verify, no_shortcut, no_symmetry) -> int:
+    return ((ORDERED if ordered else 0) | (VERIFY if verify else 0) | (NO_SHORTCUT if no_shortcut else 0)
+            | (NO_SYMMETRY if no_symmetry else 0))
+
+
 def count_ex(n: int, variant="skolem", ordered: bool = False, verify: bool = False,
              no_shortcut: bool = False, tuning: Optional[Dict] = None, stream=None,
-             progress: Optional[Callable[[int, int], Optional[bool]]] = None) -> CountResult:
+             progress: Optional[Callable[[int, int], Optional[bool]]] = None,
+             no_symmetry: bool = False) -> CountResult:
     """Exact count (reflections counted once unless ``ordered``) with launch statistics."""
-    flags = (ORDERED if ordered else 0) | (VERIFY if verify else 0) | (NO_SHORTCUT if no_shortcut else 0)
+    flags = _flags(ordered, verify, no_shortcut, no_symmetry)
     out = U128()
     st = Stats()
     t = _tuning(tuning)
@@ -230,9 +239,9 @@ def count_ex(n: int, variant="skolem", ordered: bool = False, verify: bool = Fal
 
 
 def count(n: int, variant="skolem", ordered: bool = False, verify: bool = False,
-          no_shortcut: bool = False) -> int:
+          no_shortcut: bool = False, no_symmetry: bool = False) -> int:
     """Exact number of pairings (Sec. 2).  ``ordered`` counts reflections as distinct."""
-    flags = (ORDERED if ordered else 0) | (VERIFY if verify else 0) | (NO_SHORTCUT if no_shortcut else 0)
+    flags = _flags(ordered, verify, no_shortcut, no_symmetry)
     out = U128()
     _check(lib().sk_count(n, _variant(variant), flags, ctypes.byref(out)), f"sk_count(n={n})")
     return out.value()
@@ -287,18 +296,32 @@ def sign_sum_residues(n: int, variant, primes: Sequence[int], tuning: Optional[D
     return [int(x) for x in out]
 
 
-def partial_chunks(n: int, variant, log2_chunks: int, chunk_ids: Sequence[int], primes: Sequence[int],
-                   tuning: Optional[Dict] = None, stream=None) -> List[List[int]]:
-    """Per-chunk residues (see the chunk definition in include/skolem.h)."""
+def partial_chunks(n: int, variant, log2_chunks: int, chunk_ids: Sequence[int], primes,
+                   tuning: Optional[Dict] = None, stream=None, with_stats: bool = False):
+    """Per-chunk residues (see the chunk definition in include/skolem.h).
+    primes: a list of primes, or an int k for the library's k default primes.
+    With with_stats, returns (rows, stats of the call)."""
     ids = _u64_array(chunk_ids)
-    ps = _u64_array(primes)
-    out = (ctypes.c_uint64 * (len(chunk_ids) * len(primes)))()
+    if isinstance(primes, int):
+        k, ps = primes, None
+    else:
+        k, ps = len(primes), _u64_array(primes)
+    out = (ctypes.c_uint64 * (len(chunk_ids) * k))()
     t = _tuning(tuning)
-    _check(lib().sk_partial_chunks(n, _variant(variant), log2_chunks, ids, len(chunk_ids), ps, len(primes),
+    _check(lib().sk_partial_chunks(n, _variant(variant), log2_chunks, ids, len(chunk_ids), ps, k,
                                    ctypes.byref(t) if t else None, _stream_handle(stream), out),
            "sk_partial_chunks")
-    k = len(primes)
-    return [[int(out[c * k + i]) for i in range(k)] for c in range(len(chunk_ids))]
+    rows = [[int(out[c * k + i]) for i in range(k)] for c in range(len(chunk_ids))]
+    if with_stats:
+        return rows, last_stats()
+    return rows
+
+
+def last_stats() -> Dict:
+    """Totals of this thread's last exact-sum call (sk_last_stats)."""
+    st = Stats()
+    _check(lib().sk_last_stats(ctypes.byref(st)), "sk_last_stats")
+    return st.as_dict()
 
 
 def max_chunk_bits(n: int, variant) -> int:
@@ -485,6 +508,6 @@ def last_stats_dict(st: Stats) -> Dict:
 
 
 __all__ = ["count", "count_ex", "count_batch", "autotune_batch", "pt_run", "approx", "pt_bins", "sign_sum_residues",
-           "partial_chunks", "max_chunk_bits", "set_device", "mlp_param_count", "mlp_init", "mlp_forward",
+           "partial_chunks", "last_stats", "max_chunk_bits", "set_device", "mlp_param_count", "mlp_init", "mlp_forward",
            "mlp_loss_grad", "mlp_train", "mlp_mh_step", "PROPOSAL_UNIFORM", "PROPOSAL_LEARNED",
            "SkolemError", "SKOLEM", "LANGFORD", "HOOKED", "lib", "EXPORTED"]

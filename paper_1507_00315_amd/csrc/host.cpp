@@ -99,6 +99,8 @@ static bool is_prime_u64(uint64_t x)
 // The first `count` primes below 2^46, skipping the first `skip` of them.
 static std::vector<uint64_t> default_primes(int count, int skip)
 {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
     static std::vector<uint64_t> cache;
     const int need = count + skip;
     uint64_t x = cache.empty() ? ((1ull << 46) - 1) : cache.back() - 2;
@@ -191,6 +193,19 @@ static bool existence(int n, int v)
     return r == 2 || r == 3;
 }
 
+// Lemma 2.4 generalised to every variant: negating the sign variables at even
+// positions multiplies prod x by (-1)^(even positions in P) and f_k by -1 when
+// d_k is odd (exactly one end of each pair is even), by +1 when d_k is even.
+// The term is invariant when the total exponent is even -- for Skolem,
+// Langford and hooked pairings exactly the existence conditions of Sec. 1.1.
+static bool hat_symmetric(const Plan& P)
+{
+    int e = 0;
+    for (int i = 0; i < P.m; ++i) e += (P.pos[i] % 2 == 0);
+    for (int k = 0; k < P.n; ++k) e += (P.d[k] % 2 == 1);
+    return e % 2 == 0;
+}
+
 static sk_status make_plan(int n, int variant, Plan& P)
 {
     if (variant < 0 || variant > 2) return SK_EINVAL;
@@ -269,6 +284,9 @@ struct SumRequest {
     int kernel = 0;  // 0 best, 1 reference, 2 tuned
     sk_progress_fn progress = nullptr;
     void* progress_ctx = nullptr;
+    // total mode: evaluate only the chunks whose highest chunk variable (an
+    // even position) is +1, and double (valid when hat_symmetric)
+    bool half = false;
 };
 
 // ------------------------------------------------------------------ kernels
@@ -351,6 +369,8 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
         jb = std::max(0, std::min(jb, P.n_job));
         nchunks = 1ull << (P.n_job - jb);
     }
+    const bool half = !listed && R.half && nchunks >= 2;
+    if (half) nchunks >>= 1;
     const uint64_t terms_per_chunk = 1ull << (P.n_lane + P.n_walk + jb);
     const int nbatches = (np + batch - 1) / batch;
     const uint64_t terms_total = nchunks * terms_per_chunk * (uint64_t)nbatches;
@@ -458,10 +478,13 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
             }
         }
     }
+    if (half)
+        for (int i = 0; i < np; ++i) out[i] = (uint64_t)(((u128)out[i] * 2) % R.primes[i]);
     st.terms += nchunks * terms_per_chunk;
     st.chunks += nchunks;
     st.log2_chunk_terms = P.n_lane + P.n_walk + jb;
     st.kernel_variant = kv;
+    st.symmetry_halved = half ? 1 : 0;
 done:
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -529,6 +552,7 @@ struct BatchJob {
     std::vector<uint64_t> primes;  // primes_for(n) of them
     std::vector<uint64_t> res;     // out: kernel-sum residues
     uint64_t terms = 0;
+    bool half = false;             // Lemma 2.4 half (see SumRequest::half)
 };
 
 // One persistent launch over the chunks of every job.  probe_shift > 0 runs
@@ -563,6 +587,8 @@ static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t
             a.inst[b].pinv[i] = 1.0 / (double)jobs[b].primes[i];
         }
         uint64_t total = 1ull << (P.n_job - jb);
+        if (jobs[b].half && total < 2) jobs[b].half = false;
+        if (jobs[b].half) total >>= 1;
         uint64_t use = std::max<uint64_t>(1, total >> probe_shift);
         nch[b] = use;
         jobs[b].terms = use << (P.n_lane + P.n_walk + jb);
@@ -614,6 +640,9 @@ static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t
             j.res[i] = (uint64_t)(((u128)j.res[i] + r) % j.primes[i]);
         }
     }
+    for (auto& j : jobs)
+        if (j.half)
+            for (size_t i = 0; i < j.primes.size(); ++i) j.res[i] = (uint64_t)(((u128)j.res[i] * 2) % j.primes[i]);
     if (kernel_ms) *kernel_ms = ms;
     st.kernel_ms += ms;
     st.launches += 1;
@@ -621,6 +650,8 @@ static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t
     for (auto& j : jobs) st.terms += j.terms;
     st.log2_chunk_terms = log2_chunk;
     st.kernel_variant = 3;
+    for (auto& j : jobs)
+        if (j.half) st.symmetry_halved = 1;
 done:
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -777,6 +808,7 @@ static sk_status count_impl(int n, int variant, unsigned flags, const sk_tuning*
             R.stream = (hipStream_t)stream;
             R.progress = progress;
             R.progress_ctx = pctx;
+            R.half = !(flags & SK_NO_SYMMETRY) && hat_symmetric(P);
             std::vector<uint64_t> res;
             s = run_sum(R, res, st);
             if (s != SK_OK) return s;
@@ -874,6 +906,7 @@ sk_status sk_count_batch(const sk_instance* inst, size_t k, const sk_tuning* tun
                 if (pass == 1 && !(inst[i].flags & SK_VERIFY)) continue;
                 BatchJob j;
                 j.plan = &plans[i];
+                j.half = !(inst[i].flags & SK_NO_SYMMETRY) && hat_symmetric(plans[i]);
                 const int np = primes_for(plans[i].n);
                 j.primes = default_primes(np, pass * np);
                 jobs.push_back(j);
@@ -998,6 +1031,7 @@ sk_status sk_describe(int n, int variant, sk_plan_desc* out)
     out->halved = P.halved;
     out->primes = primes_needed(n);
     for (int i = 0; i < 32; ++i) out->slot_factor[i] = (i < 4 * P.nq) ? P.slot[i].pad : -1;
+    out->symmetric = hat_symmetric(P) ? 1 : 0;
     return SK_OK;
 }
 
@@ -1005,7 +1039,12 @@ sk_status sk_partial_chunks(int n, int variant, int log2_chunks, const uint64_t*
                             const uint64_t* primes, int nprimes, const sk_tuning* tune, void* stream,
                             uint64_t* residues_out)
 {
-    if (!chunk_ids || !primes || !residues_out || nprimes < 1 || nprimes > 2 * kMaxPrimes) return SK_EINVAL;
+    if (!chunk_ids || !residues_out || nprimes < 1 || nprimes > 2 * kMaxPrimes) return SK_EINVAL;
+    std::vector<uint64_t> dflt;
+    if (!primes) {
+        dflt = default_primes(nprimes, 0);
+        primes = dflt.data();
+    }
     Plan P;
     sk_status s = make_plan(n, variant, P);
     if (s != SK_OK) return s;
@@ -1030,6 +1069,13 @@ sk_status sk_partial_chunks(int n, int variant, int log2_chunks, const uint64_t*
             residues_out[c * nprimes + i] =
                 mulmod(res[c * nprimes + i], powmod(2, (uint64_t)P.halved, primes[i]), primes[i]);
     g_stats = st;
+    return SK_OK;
+}
+
+sk_status sk_last_stats(sk_stats* out)
+{
+    if (!out) return SK_EINVAL;
+    *out = g_stats;
     return SK_OK;
 }
 

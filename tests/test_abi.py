@@ -70,3 +70,13 @@ def test_network_size_and_init_are_host_only():
     W1 = a[:256 * 130]
     assert abs(W1.std() * (130 ** 0.5) - 1.0) < 0.02 and abs(W1.mean()) < 0.01
     assert (a[256 * 130:256 * 131] == 0).all()  # b1
+
+
+def test_lemma_2_4_symmetry_matches_existence_conditions():
+    # negating the even positions leaves the term invariant exactly when the
+    # existence conditions of Sec. 1.1 hold (host-side plan, no GPU)
+    for n in range(2, 33):
+        for v, ok in (("skolem", n % 4 in (0, 1)), ("langford", n % 4 in (0, 3)), ("hooked", n % 4 in (2, 3))):
+            if v == "hooked" and n > 31:
+                continue
+            assert sk.describe(n, v)["symmetric"] == int(ok), (v, n)

@@ -239,3 +239,18 @@ def test_l28_slice_chunks_match_cpu_recomputation():
     _say("l28 slice: 16 chunks of 2^31 terms")
     rows = sk.partial_chunks(g["n"], g["variant"], g["log2_chunks"], ids, [g["prime"]])
     assert [r[0] for r in rows] == [c["residue"] for c in g["chunks"]]
+
+
+@pytest.mark.parametrize("variant,n", [("skolem", 13), ("langford", 12), ("hooked", 11), ("skolem", 16)])
+def test_lemma_2_4_half_equals_full_sum(variant, n):
+    """The default count evaluates the half of the sign vectors with the top
+    chunk variable (an even position) at +1 and doubles it; the full sum must
+    give the same count, with twice the sign vectors evaluated."""
+    _say("symmetry", variant, n)
+    a = sk.count_ex(n, variant, ordered=True)
+    b = sk.count_ex(n, variant, ordered=True, no_symmetry=True)
+    assert a.count == b.count
+    if n <= 13:
+        assert a.count == O.count_backtrack(n, variant, threads=8)
+    assert a.stats["symmetry_halved"] == 1 and b.stats["symmetry_halved"] == 0
+    assert 2 * a.stats["terms"] == b.stats["terms"]

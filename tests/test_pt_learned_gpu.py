@@ -41,12 +41,12 @@ def _learned(**kw):
 def test_learned_estimate_within_error_of_exact(variant, n):
     betas = [0.0] + [0.25 * 1.45 ** i for i in range(12)]
     _say("learned pt", variant, n)
-    est, se, st = sk.approx(n, variant, betas, ladders=64, iterations=1 << 14, seed=99,
-                            proposal=sk.PROPOSAL_LEARNED, learned=_learned())
+    est, se, st = sk.approx(n, variant, betas, ladders=64, iterations=1 << 17, seed=99,
+                            proposal=sk.PROPOSAL_LEARNED, learned=_learned(train_iterations=1 << 15))
     exact = O.reported(O.count_backtrack(n, variant, threads=8), n, variant)
     _say("  estimate", est, "+-", se, "exact", exact, "learned moves", st["learned_moves"],
          "accept", [round(x, 3) for x in st["learned_accept"]], "train loss", st["train_loss"])
-    assert st["learned_moves"] == (1 << 14) // 8
+    assert st["learned_moves"] == (1 << 17) // 8
     assert abs(est - exact) < max(4 * se, 0.005 * exact)
     assert st["train_ms"] > 0 and st["gpu_ms"] > st["train_ms"]
 
@@ -97,14 +97,15 @@ def test_training_gains_over_untrained_network():
     """Rate of accepted configuration-changing learned moves, trained network
     against the same network untrained (Table 6's S(12) ladder)."""
     n = 12
-    common = dict(ladders=64, iterations=1 << 13, seed=2024, proposal=sk.PROPOSAL_LEARNED)
+    common = dict(ladders=64, iterations=1 << 16, seed=2024, proposal=sk.PROPOSAL_LEARNED)
     P = sk.mlp_init(n, "skolem", 128, 128, seed=8)
     est0, se0, st0 = sk.approx(n, "skolem", TABLE6_BETAS, **common,
-                               learned=_learned(hidden1=128, hidden2=128, params=P.copy(), train_steps=0))
+                               learned=_learned(hidden1=128, hidden2=128, params=P.copy(), train_steps=0,
+                                                train_iterations=1 << 14))
     est1, se1, st1 = sk.approx(n, "skolem", TABLE6_BETAS, **common,
                                learned=_learned(hidden1=128, hidden2=128, params=P, train_iterations=1 << 14,
                                                 snapshots=8, train_steps=600, minibatch=512))
-    plain = sk.approx(n, "skolem", TABLE6_BETAS, ladders=64, iterations=1 << 13, seed=2024,
+    plain = sk.approx(n, "skolem", TABLE6_BETAS, ladders=64, iterations=1 << 16, seed=2024,
                       burn_in=1 << 14)[2]
     _say("untrained accept", [round(x, 3) for x in st0["learned_accept"]])
     _say("trained   accept", [round(x, 3) for x in st1["learned_accept"]], "loss", st1["train_loss"])
