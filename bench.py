@@ -76,11 +76,23 @@ def valu_per_term(desc) -> int:
     NP packed adds A + B, NQ packed pair products, NQ SDWA quad products, NQ
     conversions to fp64, NQ - G exact group products, the exact high/low split
     of g0 g1 (G >= 2), and per prime c(G) residue/accumulate instructions
-    (G = 1: 4; G = 2: 5; each further group: 6)."""
+    (G = 1: 4; G = 2: 4 plus one low-part add shared by all primes; G = 3: 11;
+    each further group: 6 more)."""
     nq, G, P = desc["quads"], desc["groups"], desc["primes_used"]
     np_ = 2 * nq
-    per_prime = {1: 4, 2: 5}.get(G, 5 + 6 * (G - 2))
-    return np_ + 3 * nq + (nq - G) + (2 if G >= 2 else 0) + P * per_prime
+    if G == 1:
+        chain = 4 * P
+    elif G == 2:
+        chain = 4 * P + 1
+    else:
+        chain = P * (11 + 6 * (G - 3))
+    return np_ + 3 * nq + (nq - G) + (2 if G >= 2 else 0) + chain
+
+
+def ring_ops_per_term(n: int, P: int) -> int:
+    """The method's own work per sign vector: n pair-sum updates, n - 1
+    modular multiplications and one accumulate per prime."""
+    return n + P * (n - 1) + P
 
 
 def cpu_baseline(instances, threads):
@@ -90,7 +102,7 @@ def cpu_baseline(instances, threads):
     O.build(force=False)
     variant, n = max(instances, key=lambda vn: vn[1])
     pos, _ = O.instance(n, variant)
-    free_bits = 28 if n >= 20 else 26
+    free_bits = 32 if n >= 20 else 28
     fixed = {pos[0]: 1}
     for q in pos[1 + free_bits:]:
         fixed[q] = 1
@@ -99,52 +111,86 @@ def cpu_baseline(instances, threads):
     t0 = time.time()
     O.chunk_partial(n, variant, fixed, p, "gray", threads=threads)
     dt = time.time() - t0
-    return {"value": terms / dt, "unit": "terms/s", "cores": threads, "kind": "oracle",
+    return {"value": terms / dt, "unit": "terms/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
             "sample": f"{variant} n={n}: Gray-code partial sum over 2^{len(pos) - len(fixed)} sign vectors "
                       f"(x at positions above {pos[free_bits]} fixed), one prime, {threads} threads, "
                       f"{dt:.1f} s"}
 
 
 def config5_ladder():
-    """48 levels: beta = 0 (the relaxed problem's exact normaliser) and 47
-    geometric steps from 0.05 to 6."""
-    return [0.0] + [0.05 * (6.0 / 0.05) ** (j / 46) for j in range(47)]
+    """The 48 geometric replicas 0.05 * 120^(j/47), j = 0..47 (0.05 .. 6),
+    below them the beta = 0 level whose samples give Z(beta_1) / Z(0); the
+    terminal factor is the fraction of E = 0 samples at beta = 6."""
+    return [0.0] + [0.05 * 120.0 ** (j / 47) for j in range(48)]
 
 
-def pt_bench(sk, want, iters: int, ladders: int, learned_cfg: dict, seed: int = 1507):
-    """Tempering estimates (Sec. 3) on the 48-level ladder: relative error
-    against the printed S(20), S(24) and GPU seconds, plain uniform moves and
-    the learned proposal; S(32) beside the paper's own estimate.  Each run
-    burns in (and, learned, trains on) iters / 4 iterations first."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def pt_bench(sk, want, plain_iters, learned_iters, ladders: int, learned_cfg: dict, seed: int = 1507,
+             cpu_pt: bool = True):
+    """Tempering estimates (Sec. 3) on the 49-level ladder: relative error
+    against the printed S(20), S(24) and GPU seconds, as a curve over run
+    lengths, for plain uniform moves and with the learned proposal; S(32)
+    beside the paper's own estimate.  Every run first burns in (learned: and
+    trains on) a quarter of its recorded iterations."""
     betas = config5_ladder()
     runs = []
-    for n in (20, 24, 32):
+
+    def one(n, name, iters):
         exact = want.get(("skolem", n))
-        for name in ("plain", "learned"):
-            kw = dict(ladders=ladders, iterations=iters, seed=seed + n, burn_in=0 if name == "learned" else iters // 4)
-            if name == "learned":
-                kw["proposal"] = sk.PROPOSAL_LEARNED
-                kw["learned"] = dict(learned_cfg, train_iterations=iters // 4)
-            t0 = time.time()
-            est, se, st = sk.approx(n, "skolem", betas, **kw)
-            rec = {"n": n, "proposal": name, "estimate": est, "std_error": se, "rel_std_error": se / est if est else None,
-                   "gpu_s": st["gpu_ms"] * 1e-3, "train_gpu_s": st["train_ms"] * 1e-3, "wall_s": time.time() - t0,
-                   "iterations": iters, "ladders": ladders}
-            if exact:
-                rec["exact"] = exact
-                rec["rel_error"] = abs(est - exact) / exact
-            if name == "learned":
-                rec["learned_moves"] = st["learned_moves"]
-                rec["learned_accept_top"] = st["learned_accept"][-1]
-                rec["learned_accept_mean"] = sum(st["learned_accept"][learned_cfg["first_level"]:]) / (
-                    len(betas) - learned_cfg["first_level"])
-                rec["train_loss"] = st["train_loss"]
-            rec["plain_move_accept_top"] = st["move_accept"][-1]
-            log(f"pt {name} S({n}): {est:.6g} +- {se:.3g}" + (f" (exact {exact}, rel err {rec['rel_error']:.2e})"
-                                                               if exact else "") + f"  gpu {rec['gpu_s']:.2f} s")
-            runs.append(rec)
-    return {"ladder": "beta_0 = 0, then 47 geometric levels 0.05 .. 6", "levels": len(betas), "runs": runs,
-            "paper_S32_estimate": 2.2e26}
+        kw = dict(ladders=ladders, iterations=iters, seed=seed + n)
+        if name == "learned":
+            kw["proposal"] = sk.PROPOSAL_LEARNED
+            kw["learned"] = dict(learned_cfg, train_iterations=iters // 4)
+        else:
+            kw["burn_in"] = iters // 4
+        t0 = time.time()
+        est, se, st = sk.approx(n, "skolem", betas, **kw)
+        rec = {"n": n, "proposal": name, "iterations": iters, "ladders": ladders, "estimate": est, "std_error": se,
+               "rel_std_error": se / est if est else None, "gpu_s": st["gpu_ms"] * 1e-3,
+               "wall_s": time.time() - t0, "level_moves_per_gpu_s": st["moves"] / max(st["gpu_ms"] * 1e-3, 1e-12)}
+        if exact:
+            rec["exact"] = exact
+            rec["rel_error"] = abs(est - exact) / exact
+        if name == "learned":
+            j0 = learned_cfg["first_level"]
+            rec.update({"train_gpu_s": st["train_ms"] * 1e-3, "learned_moves": st["learned_moves"],
+                        "learned_accept_mean": sum(st["learned_accept"][j0:]) / (len(betas) - j0),
+                        "plain_accept_mean_same_levels": sum(st["move_accept"][j0:]) / (len(betas) - j0),
+                        "train_loss": st["train_loss"]})
+        log(f"pt {name:7s} S({n}) 2^{iters.bit_length() - 1} it: {est:.6g} +- {se:.3g}"
+            + (f"  rel err {rec['rel_error']:.2e}" if exact else "") + f"  gpu {rec['gpu_s']:.3f} s")
+        runs.append(rec)
+
+    for n in (20, 24):
+        for it in plain_iters:
+            one(n, "plain", it)
+        for it in learned_iters:
+            one(n, "learned", it)
+    one(32, "plain", plain_iters[-1])
+    one(32, "learned", learned_iters[-1])
+    cpu = None
+    if cpu_pt:
+        import oracle as O
+        O.build(force=False)
+        iters = 1 << 20
+        t0 = time.time()
+        O.pt_ladder(32, "skolem", betas, iters, seed, ladder=0, schedule="even_odd")
+        dt = time.time() - t0
+        cpu = {"value": iters * len(betas) / dt, "unit": "level-moves/s", "cores": 1, "kind": "oracle",
+               "cpu": cpu_model(), "sample": f"one ladder of S(32), {len(betas)} levels, 2^20 iterations, {dt:.1f} s"}
+    return {"ladder": "beta = 0, then 48 geometric levels 0.05 * 120^(j/47)", "levels": len(betas),
+            "learned_config": {k: v for k, v in learned_cfg.items() if k != "params"}, "runs": runs,
+            "paper_S32_estimate": 2.2e26, "cpu_baseline": cpu}
 
 
 def main():
@@ -159,11 +205,23 @@ def main():
     ap.add_argument("--separate", action="store_true", help="batch workload as one launch per instance")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-pt", action="store_true", help="skip the tempering estimates")
-    ap.add_argument("--pt-iters", type=int, default=1 << 14)
+    ap.add_argument("--pt-plain-log2", default="14,16,18,20", help="log2 recorded iterations, plain runs")
+    ap.add_argument("--pt-learned-log2", default="14,16,18", help="log2 recorded iterations, learned runs")
     ap.add_argument("--pt-ladders", type=int, default=1024)
-    ap.add_argument("--pt-learned-every", type=int, default=64)
-    ap.add_argument("--pt-learned-first", type=int, default=24)
+    ap.add_argument("--pt-learned-every", type=int, default=256)
+    ap.add_argument("--pt-learned-first", type=int, default=36)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {src.numel() * 4} bytes")
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the exact sum shards by chunk ranges across GPUs, see DESIGN.md", file=sys.stderr)
@@ -252,6 +310,7 @@ def main():
     # count of the tuned body) x sign vectors / launch durations measured with
     # HIP events on the launch stream.
     instr = 0.0
+    ring = 0.0
     for v, n in instances:
         d = sk.describe(n, v)
         d["primes_used"] = d["primes"]
@@ -259,6 +318,7 @@ def main():
         # sign vectors the kernel evaluates (half of 2^(2n-1) where Lemma 2.4 applies)
         terms_inst = terms_per_step if slice_ids is not None else (1 << (2 * n - 1)) >> d["symmetric"]
         instr += terms_inst * instr_per
+        ring += terms_inst * ring_ops_per_term(n, d["primes"])
     kms = sum(s["kernel_ms"] for st in results for s in stats_of(st)) / args.steps
     launches = sum(s["launches"] for st in results for s in stats_of(st)) // args.steps
     achieved = instr / (kms * 1e-3) if kms > 0 else 0.0
@@ -290,7 +350,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "VALU lane-instr/s",
                      "frac": achieved / PEAK_LANE_OPS, "traffic": None, "kernel": kernel_name,
                      "valu_instr_per_term": instr_per_term, "terms_per_s_kernel": terms_per_step / (kms * 1e-3),
-                     "launches": launches, "avg_launch_ms": kms / max(launches, 1)},
+                     "launches": launches, "avg_launch_ms": kms / max(launches, 1),
+                     "ring_ops_per_term": ring / terms_per_step,
+                     "ring_ops_per_s": ring / (kms * 1e-3) if kms > 0 else 0.0},
     }
     if slice_ids is not None:
         full_chunks = 1 << L28_CHUNK_BITS
@@ -302,7 +364,9 @@ def main():
         learned_cfg = dict(hidden1=256, hidden2=256, first_level=args.pt_learned_first,
                            plain_per_learned=args.pt_learned_every, snapshots=8, train_steps=400, minibatch=1024,
                            lr=1e-3, init_seed=1)
-        line["pt"] = pt_bench(sk, want, args.pt_iters, args.pt_ladders, learned_cfg)
+        line["pt"] = pt_bench(sk, want, [1 << int(x) for x in args.pt_plain_log2.split(",")],
+                              [1 << int(x) for x in args.pt_learned_log2.split(",")], args.pt_ladders, learned_cfg,
+                              cpu_pt=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log("cpu baseline ...")

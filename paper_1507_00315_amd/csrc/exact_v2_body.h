@@ -279,10 +279,13 @@ struct ExactV2 {
         }
     }
 
-    // Term at the current state: acc += sign * prod_k f'_k (mod p_i).
+    // Term at the current state: acc += sign * prod_k f'_k (mod p_i).  With
+    // two product groups the exact low part l of g0 g1 does not depend on the
+    // prime; it is summed once in accl and added to every prime's sum when the
+    // block is reduced.
     template <bool NEG>
     __device__ static __forceinline__ void term(const uint32_t (&A)[NP], const Uniform& u, const double (&pr)[P],
-                                                const double (&pinv)[P], double (&acc)[P])
+                                                const double (&pinv)[P], double (&acc)[P], double& accl)
     {
         uint32_t f[NP];
         static_for<0, NP>([&](auto pc) {
@@ -316,7 +319,6 @@ struct ExactV2 {
                 const double s = __builtin_fma(quot_nearest(h, pinv[i]), -pr[i], h);
                 if constexpr (G == 2) {
                     acc[i] = NEG ? acc[i] - s : acc[i] + s;
-                    acc[i] = NEG ? acc[i] - l : acc[i] + l;
                 } else {
                     double r = s + l;
                     static_for<2, G>([&](auto gc) {
@@ -333,6 +335,7 @@ struct ExactV2 {
                     });
                 }
             });
+            if constexpr (G == 2) accl = NEG ? accl - l : accl + l;
         }
     }
 };
@@ -403,17 +406,19 @@ __device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const dou
         constexpr uint64_t nblocks = 1ull << (W - (INNER + 1));
         for (uint64_t ds = 0; ds < nblocks; ++ds) {
             if (ds > 0) K::template flip_walk_bit<INNER + 1>(u, INNER + 1 + (int)__builtin_ctzll(ds));
+            // |accl| <= D * 2^43 (low parts of products below 2^96)
+            double accl = 0.0;
             static_for<0, D>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 if constexpr (i > 0) {
                     if constexpr (K::ctz_ce(i) < INNER) K::template flip_inner<i>(u);
                     else K::template flip_outer<2 + INNER>(u);
                 }
-                K::template term<(i & 1) != 0>(A, u, pr, pinv, acc);
+                K::template term<(i & 1) != 0>(A, u, pr, pinv, acc, accl);
             });
             static_for<0, P>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
-                acc[i] = reduce_balanced(acc[i], pr[i], pinv[i]);
+                acc[i] = reduce_balanced(acc[i] + accl, pr[i], pinv[i]);
             });
         }
         static_for<0, P>([&](auto ic) {

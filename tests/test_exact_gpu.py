@@ -52,9 +52,12 @@ def test_counts_small_n_all_variants(variant):
 def test_config1_skolem_12_and_zeros():
     """S(12) over 2^23 sign vectors, two primes; S(10) = S(11) = 0 (Table 7;
     existence, Sec. 1.1)."""
-    r = sk.count_ex(12, "skolem", tuning={"primes": 2})
+    r = sk.count_ex(12, "skolem", tuning={"primes": 2}, no_symmetry=True)
     assert r.count == 227968
-    assert r.stats["nprimes"] == 2 and r.stats["terms"] == 1 << 23
+    assert r.stats["nprimes"] == 2 and r.stats["terms"] == 1 << 23 and r.stats["symmetry_halved"] == 0
+    # by default only the Lemma 2.4 half is evaluated
+    h = sk.count_ex(12, "skolem", tuning={"primes": 2})
+    assert h.count == 227968 and h.stats["terms"] == 1 << 22 and h.stats["symmetry_halved"] == 1
     for n in (10, 11):
         assert sk.count(n, "skolem", no_shortcut=True) == 0
     assert O.is_valid_pairing(O.skolem_construction(12), 12, "skolem")

@@ -166,8 +166,8 @@ def test_mh_step_matches_oracle(variant, n, h1, h2):
     r = sk.mlp_mh_step(n, variant, P, S, betas, wp, wa, h1, h2)
     compared = 0
     for i in range(B):
-        a = list(S[i])
-        prop = list(r["proposed"][i])
+        a = [int(x) for x in S[i]]
+        prop = [int(x) for x in r["proposed"][i]]
         diff = [k for k in range(n) if prop[k] != a[k]]
         assert len(diff) <= 1
         jo, margin, lq = _oracle_decision(Pd, g, a, betas[i], int(wp[i]), int(wa[i]))
@@ -197,7 +197,7 @@ def test_mh_step_matches_oracle(variant, n, h1, h2):
             if u > 0 and abs(math.log(u) - min(0.0, log_alpha)) > 1e-3:
                 acc = math.log(u) < min(0.0, log_alpha)
                 assert bool(r["accepted"][i]) == acc, i
-                assert list(r["states"][i]) == (b if acc else a)
+                assert [int(x) for x in r["states"][i]] == (b if acc else a)
                 compared += 1
     _say("  decisions compared:", compared, "of", B)
     assert compared > 0.9 * B
