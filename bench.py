@@ -14,6 +14,7 @@ Workloads (all inputs are the problem statements themselves: no data files):
   l24    Langford n = 24
   s20    Skolem n = 20;  l20  Langford n = 20
   s12    Skolem n = 12, two primes (the small correctness case)
+  s25    Skolem n = 25 (2^49 sign vectors; the paper used four GPUs)
   l28slice  Langford n = 28: a seeded 1/4096 subset of its 2^24 prefix chunks
          (2^43 sign vectors) with the three primes a full count needs; the
          projected full-count time is reported
@@ -41,8 +42,42 @@ WORKLOADS = {
     "l20": [("langford", 20)],
     "s12": [("skolem", 12)],
     "l28slice": [("langford", 28)],
+    "s25": [("skolem", 25)],
 }
 L28_CHUNK_BITS, L28_SLICE = 24, 4096
+
+
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs (KiB per
+# dispatch), scaled by what the same counters read for a plain 1 GiB device copy
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources they
+# were taken on: the fingerprint is a SHA-256 over those sources, and a changed
+# kernel reports traffic null until the counters are taken again.
+KERNEL_SOURCES = {
+    "exact_batch_kernel": ["exact_batch.hip", "sk_batch.h", "exact_v2_body.h", "exact_common.h", "sk_plan.h",
+                           "sk_internal.h"],
+    "exact_v2_kernel": ["exact_v2_inst.hip", "exact_v2_body.h", "exact_common.h", "sk_plan.h", "sk_internal.h"],
+}
+MEASURED_TRAFFIC = {
+    # (kernel, workload): (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
+    ("exact_v2_kernel", "s20"): ("8c5fbd4b96e6735d", 1598.1875, 6272.0),
+}
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
+
+
+def kernel_fingerprint(kernel: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(ROOT, "paper_1507_00315_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch(kernel: str, workload: str):
+    rec = MEASURED_TRAFFIC.get((kernel, workload))
+    if rec is None or rec[0] != kernel_fingerprint(kernel):
+        return None
+    return (rec[1] * FETCH_FACTOR + rec[2] * WRITE_FACTOR) * 1024
 
 
 def log(*a):
@@ -202,6 +237,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--log2-chunk", type=int, default=0)
     ap.add_argument("--kernel", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0, help="waves per launch (with --log2-chunk)")
     ap.add_argument("--separate", action="store_true", help="batch workload as one launch per instance")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-pt", action="store_true", help="skip the tempering estimates")
@@ -235,7 +271,7 @@ def main():
         sync = lambda: None  # noqa: E731
 
     instances = WORKLOADS[args.workload]
-    tuning = {"log2_chunk_terms": args.log2_chunk, "kernel": args.kernel}
+    tuning = {"log2_chunk_terms": args.log2_chunk, "kernel": args.kernel, "waves_per_launch": args.waves}
     if args.workload == "s12":
         tuning["primes"] = 2
     want = expected_values()
@@ -348,7 +384,8 @@ def main():
                                                      sum(1 << (2 * n - 1) for v, n in instances)),
                    "results_match_expected": all_ok},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "VALU lane-instr/s",
-                     "frac": achieved / PEAK_LANE_OPS, "traffic": None, "kernel": kernel_name,
+                     "frac": achieved / PEAK_LANE_OPS, "traffic": traffic_per_launch(kernel_name, args.workload),
+                     "kernel": kernel_name,
                      "valu_instr_per_term": instr_per_term, "terms_per_s_kernel": terms_per_step / (kms * 1e-3),
                      "launches": launches, "avg_launch_ms": kms / max(launches, 1),
                      "ring_ops_per_term": ring / terms_per_step,

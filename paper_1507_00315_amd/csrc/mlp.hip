@@ -134,15 +134,21 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs a)
     }
 }
 
-// column sums: out[n] (+)= alpha * sum_m Y[m * ld + n]
+// column sums: out[n] = alpha * sum_m Y[m * ld + n].  One block per 64
+// columns: wave w adds rows w, w + 4, ... with lane = column (coalesced
+// 256-byte rows), the four partial sums meet in LDS.
 __global__ void __launch_bounds__(256) colsum_kernel(const float* __restrict__ Y, long M, long N, long ld,
                                                      float alpha, float* __restrict__ out)
 {
-    const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+    __shared__ double part[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long n = (long)blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (long m = 0; m < M; ++m) s += Y[m * ld + n];
-    out[n] = (float)(alpha * s);
+    if (n < N)
+        for (long m = wv; m < M; m += 4) s += Y[m * ld + n];
+    part[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && n < N) out[n] = (float)(alpha * (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]));
 }
 
 // ------------------------------------------------------------------ softmax
@@ -447,7 +453,7 @@ hipError_t launch_gemm(const GemmArgs& a, hipStream_t s)
 
 hipError_t launch_colsum(const float* Y, long M, long N, long ld, float alpha, float* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, Y, M, N, ld, alpha, out);
+    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((N + 63) / 64)), dim3(256), 0, s, Y, M, N, ld, alpha, out);
     return hipGetLastError();
 }
 
