@@ -13,7 +13,7 @@ constexpr int kMaxSlots = 32;   // factor slots (4 per quad)
 constexpr int kMaxPrimes = 4;   // primes per pass
 constexpr int kLaneBits = 6;    // 64 lanes of a wavefront = 6 sign variables
 
-// Exact fp64 modular arithmetic needs primes in (2^45, 2^46): see exact.hip.
+// Exact fp64 modular arithmetic needs primes in (2^45, 2^46): see exact_common.h.
 constexpr double kPrimeLo = 35184372088832.0;  // 2^45
 constexpr double kPrimeHi = 70368744177664.0;  // 2^46
 

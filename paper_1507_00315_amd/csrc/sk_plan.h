@@ -205,16 +205,20 @@ __host__ __device__ constexpr PlanCE make_plan_ce(int n, int variant, int walk_c
 
 // Fewest primes in (2^45, 2^46) whose product exceeds n! * 2^8.  Every ordered
 // count is at most n!: the leftmost uncovered position always starts a new
-// pair, so a pairing is fixed by the order in which labels are used.
+// pair, so a pairing is fixed by the order in which labels are used.  The
+// library's primes are the largest below 2^46, each above 2^45.999, so k of
+// them cover 45.999 k bits; log2(n!) is tabulated in thousandths of a bit,
+// rounded up.
 __host__ __device__ constexpr int primes_for(int n)
 {
-    // sum of log2(i) for i <= n, bounded above by integer bit lengths is too
-    // coarse; use a table of ceil(log2(n!)) for n <= 32.
-    constexpr int lg_fact[33] = {0,  0,  1,  3,  5,  7,  10, 13, 16, 19, 22, 26, 29, 33, 37, 41, 45,
-                                 49, 53, 57, 62, 66, 70, 75, 80, 84, 89, 94, 98, 103, 108, 113, 118};
-    const int bits = lg_fact[n < 0 ? 0 : (n > 32 ? 32 : n)] + 8;
-    int k = (bits + 44) / 45;
-    return k < 1 ? 1 : (k > kMaxPrimes ? kMaxPrimes : k);
+    constexpr int lg_fact_milli[33] = {0,     0,     1000,  2585,  4585,  6907,  9492,  12300, 15300,
+                                       18470, 21792, 25251, 28836, 32536, 36344, 40251, 44251, 48338,
+                                       52508, 56756, 61078, 65470, 69930, 74453, 79038, 83682, 88382,
+                                       93137, 97945, 102803, 107710, 112664, 117664};
+    const int need = lg_fact_milli[n < 0 ? 0 : (n > 32 ? 32 : n)] + 8000;
+    int k = 1;
+    while (k < kMaxPrimes && k * 45999 < need) ++k;
+    return k;
 }
 
 }  // namespace sk

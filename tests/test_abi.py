@@ -80,3 +80,18 @@ def test_lemma_2_4_symmetry_matches_existence_conditions():
             if v == "hooked" and n > 31:
                 continue
             assert sk.describe(n, v)["symmetric"] == int(ok), (v, n)
+
+
+def test_prime_count_covers_the_count_bound():
+    # the library's k primes (the largest below 2^46) must exceed n! * 2^8, and
+    # k - 1 of them must not (fewest primes); checked with exact integers
+    import math
+    import oracle as O
+    O.build(force=False)
+    primes = O.primes_below(1 << 46, 4)
+    for v in ("skolem", "langford"):
+        for n in range(1, 33):
+            k = sk.describe(n, v)["primes"]
+            bound = math.factorial(n) << 8
+            assert math.prod(primes[:k]) > bound, (v, n, k)
+            assert k == 1 or math.prod(primes[:k - 1]) <= bound, (v, n, k)
