@@ -58,8 +58,9 @@ KERNEL_SOURCES = {
     "exact_v2_kernel": ["exact_v2_inst.hip", "exact_v2_body.h", "exact_common.h", "sk_plan.h", "sk_internal.h"],
 }
 MEASURED_TRAFFIC = {
-    # (kernel, workload): (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact_v2_kernel", "s20"): ("8c5fbd4b96e6735d", 1598.1875, 6272.0),
+    # (kernel, workload, log2 sign vectors per work item, waves per launch):
+    #     (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
+    ("exact_batch_kernel", "batch", 24, 4096): ("35cfb254f9ec69a7", 2016.125, 10663.125),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
@@ -73,8 +74,8 @@ def kernel_fingerprint(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch(kernel: str, workload: str):
-    rec = MEASURED_TRAFFIC.get((kernel, workload))
+def traffic_per_launch(kernel: str, workload: str, log2_chunk: int, waves: int):
+    rec = MEASURED_TRAFFIC.get((kernel, workload, log2_chunk, waves))
     if rec is None or rec[0] != kernel_fingerprint(kernel):
         return None
     return (rec[1] * FETCH_FACTOR + rec[2] * WRITE_FACTOR) * 1024
@@ -320,9 +321,11 @@ def main():
                 f"check={res[-1][4]}")
         return res
 
+    launch_waves = args.waves
     if args.workload == "batch" and not args.separate and not args.no_autotune and not args.log2_chunk:
         t0 = time.time()
         best, rate = sk.autotune_batch([(n, v) for v, n in instances])
+        launch_waves = best["waves_per_launch"]
         log(f"autotune: {best} ({rate:.3e} terms/s on the probe, {time.time() - t0:.1f} s)")
     for w in range(args.warmup):
         step(f"warmup {w}")
@@ -384,7 +387,9 @@ def main():
                                                      sum(1 << (2 * n - 1) for v, n in instances)),
                    "results_match_expected": all_ok},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "VALU lane-instr/s",
-                     "frac": achieved / PEAK_LANE_OPS, "traffic": traffic_per_launch(kernel_name, args.workload),
+                     "frac": achieved / PEAK_LANE_OPS, "traffic": traffic_per_launch(kernel_name, args.workload,
+                                                               stats_of(results[0])[0]["log2_chunk_terms"],
+                                                               launch_waves),
                      "kernel": kernel_name,
                      "valu_instr_per_term": instr_per_term, "terms_per_s_kernel": terms_per_step / (kms * 1e-3),
                      "launches": launches, "avg_launch_ms": kms / max(launches, 1),

@@ -178,6 +178,22 @@ __device__ __forceinline__ int move_delta(const uint8_t* occ, int ao, int ap, in
     return de;
 }
 
+// Walks the entries j = j0, j0 + step, ... of the n x T logit matrix keeping
+// (k, c) = (j / T, j % T) up to date without a division per entry.
+struct EntryWalk {
+    int k, c, qs, rs, T;
+    __device__ EntryWalk(int j0, int step, int T_) : k(j0 / T_), c(j0 % T_), qs(step / T_), rs(step % T_), T(T_) {}
+    __device__ void next()
+    {
+        k += qs;
+        c += rs;
+        if (c >= T) {
+            c -= T;
+            ++k;
+        }
+    }
+};
+
 // placement index a' - 1 valid for pair k?
 __device__ __forceinline__ bool move_valid(const MlpGeo& g, int k, int ap)
 {
@@ -219,8 +235,9 @@ __global__ void __launch_bounds__(256) mlp_target_grad_kernel(MlpGeo g, const ui
     const int D = g.n * g.T;
     // pass 1: maxima of z and of -beta E'
     float zmax = -INFINITY, emin = INFINITY;
-    for (int j = lane; j < D; j += 64) {
-        const int k = j / g.T, ap = j % g.T + 1;
+    EntryWalk w1(lane, 64, g.T);
+    for (int j = lane; j < D; j += 64, w1.next()) {
+        const int k = w1.k, ap = w1.c + 1;
         if (!move_valid(g, k, ap)) continue;
         zmax = fmaxf(zmax, z[j]);
         const int de = move_delta(occ, s[k], ap, geo_diff(g, k));
@@ -230,8 +247,9 @@ __global__ void __launch_bounds__(256) mlp_target_grad_kernel(MlpGeo g, const ui
     emin = -wave_max(-emin);
     // pass 2: normalisers
     float zs = 0.f, ps = 0.f;
-    for (int j = lane; j < D; j += 64) {
-        const int k = j / g.T, ap = j % g.T + 1;
+    EntryWalk w2(lane, 64, g.T);
+    for (int j = lane; j < D; j += 64, w2.next()) {
+        const int k = w2.k, ap = w2.c + 1;
         if (!move_valid(g, k, ap)) continue;
         zs += __expf(z[j] - zmax);
         const int de = move_delta(occ, s[k], ap, geo_diff(g, k));
@@ -242,8 +260,9 @@ __global__ void __launch_bounds__(256) mlp_target_grad_kernel(MlpGeo g, const ui
     const float lzs = __logf(zs);
     // pass 3: gradient and loss
     float l = 0.f;
-    for (int j = lane; j < D; j += 64) {
-        const int k = j / g.T, ap = j % g.T + 1;
+    EntryWalk w3(lane, 64, g.T);
+    for (int j = lane; j < D; j += 64, w3.next()) {
+        const int k = w3.k, ap = w3.c + 1;
         if (!move_valid(g, k, ap)) {
             z[j] = 0.f;
             continue;
@@ -274,17 +293,17 @@ __global__ void __launch_bounds__(256) mlp_sample_kernel(MlpGeo g, const uint8_t
     const float* z = Z + (size_t)t * ldz;
     const int D = g.n * g.T;
     float zmax = -INFINITY;
-    for (int j = lane; j < D; j += 64) {
-        const int k = j / g.T, ap = j % g.T + 1;
-        if (move_valid(g, k, ap)) zmax = fmaxf(zmax, z[j]);
-    }
+    EntryWalk w1(lane, 64, g.T);
+    for (int j = lane; j < D; j += 64, w1.next())
+        if (move_valid(g, w1.k, w1.c + 1)) zmax = fmaxf(zmax, z[j]);
     zmax = wave_max(zmax);
     // each lane owns a contiguous run of entries [lane*R, lane*R + R)
     const int R = (D + 63) / 64;
     float part = 0.f;
-    for (int i = 0; i < R; ++i) {
+    EntryWalk w2(lane * R, 1, g.T);
+    for (int i = 0; i < R; ++i, w2.next()) {
         const int j = lane * R + i;
-        if (j < D && move_valid(g, j / g.T, j % g.T + 1)) part += __expf(z[j] - zmax);
+        if (j < D && move_valid(g, w2.k, w2.c + 1)) part += __expf(z[j] - zmax);
     }
     // exclusive prefix over lanes
     float incl = part;
@@ -302,9 +321,10 @@ __global__ void __launch_bounds__(256) mlp_sample_kernel(MlpGeo g, const uint8_t
     if (lane == owner) {
         float c = excl;
         int last_valid = -1;
-        for (int i = 0; i < R; ++i) {
+        EntryWalk w3(lane * R, 1, g.T);
+        for (int i = 0; i < R; ++i, w3.next()) {
             const int j = lane * R + i;
-            if (j >= D || !move_valid(g, j / g.T, j % g.T + 1)) continue;
+            if (j >= D || !move_valid(g, w3.k, w3.c + 1)) continue;
             last_valid = j;
             c += __expf(z[j] - zmax);
             if (c > target_mass) {
@@ -342,12 +362,14 @@ __global__ void __launch_bounds__(256) mlp_logq_kernel(MlpGeo g, const float* __
     const float* z = Z + (size_t)t * ldz;
     const int D = g.n * g.T;
     float zmax = -INFINITY;
-    for (int j = lane; j < D; j += 64)
-        if (move_valid(g, j / g.T, j % g.T + 1)) zmax = fmaxf(zmax, z[j]);
+    EntryWalk w1(lane, 64, g.T);
+    for (int j = lane; j < D; j += 64, w1.next())
+        if (move_valid(g, w1.k, w1.c + 1)) zmax = fmaxf(zmax, z[j]);
     zmax = wave_max(zmax);
     float zs = 0.f;
-    for (int j = lane; j < D; j += 64)
-        if (move_valid(g, j / g.T, j % g.T + 1)) zs += __expf(z[j] - zmax);
+    EntryWalk w2(lane, 64, g.T);
+    for (int j = lane; j < D; j += 64, w2.next())
+        if (move_valid(g, w2.k, w2.c + 1)) zs += __expf(z[j] - zmax);
     zs = wave_sumf(zs);
     if (lane == 0) logq_rev[t] = z[move_k[t] * g.T + move_old[t] - 1] - zmax - __logf(zs);
 }

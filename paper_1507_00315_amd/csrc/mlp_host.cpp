@@ -68,7 +68,7 @@ void MlpNet::release()
     free_batch();
 }
 
-sk_status MlpNet::init(const MlpGeo& geo, int h1_, int h2_)
+sk_status MlpNet::init(const MlpGeo& geo, int h1_, int h2_, hipStream_t s)
 {
     g = geo;
     din = g.T + 2 * g.n + 2;
@@ -86,8 +86,8 @@ sk_status MlpNet::init(const MlpGeo& geo, int h1_, int h2_)
     NET_HIP(hipMalloc(&Gr, count * sizeof(float)));
     NET_HIP(hipMalloc(&Mo, count * sizeof(float)));
     NET_HIP(hipMalloc(&Ve, count * sizeof(float)));
-    NET_HIP(hipMemset(Mo, 0, count * sizeof(float)));
-    NET_HIP(hipMemset(Ve, 0, count * sizeof(float)));
+    NET_HIP(hipMemsetAsync(Mo, 0, count * sizeof(float), s));
+    NET_HIP(hipMemsetAsync(Ve, 0, count * sizeof(float), s));
     adam_t = 0;
     return SK_OK;
 }
@@ -276,7 +276,7 @@ sk_status setup_net(int n, int variant, int h1, int h2, const float* params, Mlp
     MlpGeo g;
     if (!mlp_geometry(n, variant, g) || !params) return SK_EINVAL;
     if (hipSetDevice(current_device()) != hipSuccess) return SK_EDEVICE;
-    sk_status st = net.init(g, h1, h2);
+    sk_status st = net.init(g, h1, h2, s);
     if (st != SK_OK) return st;
     if (hipMemcpyAsync(net.P, params, net.count * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess)
         return SK_EDEVICE;

@@ -41,6 +41,18 @@ __device__ __forceinline__ int placement(const PtArgs& a, int d, int idx)
     return 1 + idx;
 }
 
+// The value held by lane + 1 / lane - 1 (wavefront shifts by one lane, DPP;
+// every lane is active where these are used).  At the ends of the wavefront
+// the lane keeps its own value, which the callers never use.
+__device__ __forceinline__ int from_lane_above(int x)
+{
+    return __builtin_amdgcn_update_dpp(x, x, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int from_lane_below(int x)
+{
+    return __builtin_amdgcn_update_dpp(x, x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+}
+
 __device__ __forceinline__ int pair_diff(const PtArgs& a, int k) { return a.variant == 1 ? k + 2 : k + 1; }
 
 __device__ __forceinline__ int placements_of(const PtArgs& a, int d)
@@ -61,9 +73,13 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     const int slot_bytes = a.slot_bytes;  // n placements + (top + 1) occupancies, rounded to 4
     uint8_t* slots = lds;
     uint32_t* hist = (uint32_t*)(lds + (size_t)64 * slot_bytes);  // M x H
+    uint32_t* swap_thr = hist + M * H;                              // M x H, copy of a.swap_thr
     const bool live = lane < M;
 
-    for (int i = lane; i < M * H; i += 64) hist[i] = 0;
+    for (int i = lane; i < M * H; i += 64) {
+        hist[i] = 0;
+        swap_thr[i] = a.swap_thr[i];
+    }
 
     int slot = lane;
     int E = 0;
@@ -102,8 +118,8 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     __syncthreads();
 
     for (uint64_t it = a.it_begin; it < a.it_end; ++it) {
-        // 1. record
-        if (live) hist[lane * H + E] += 1u;
+        // 1. record (LDS atomic add: no read-back, each lane owns its row)
+        if (live) atomicAdd(&hist[lane * H + E], 1u);
         // 2. move
         uint32_t r[4];
         philox4x32_10((uint32_t)it, (uint32_t)(it >> 32), ladder, (uint32_t)lane, k0, k1, r);
@@ -115,45 +131,40 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
             const int idx = (int)__umulhi(r[1], (uint32_t)placements_of(a, d));
             const int a_new = placement(a, d, idx);
             const int a_old = s[k];
-            int de = 0;
-            uint8_t o;
-            o = occ[a_old];
-            occ[a_old] = o - 1;
-            de += (o == 1);
-            o = occ[a_old + d];
-            occ[a_old + d] = o - 1;
-            de += (o == 1);
-            o = occ[a_new];
-            occ[a_new] = o + 1;
-            de -= (o == 0);
-            o = occ[a_new + d];
-            occ[a_new + d] = o + 1;
-            de -= (o == 0);
+            const int b_old = a_old + d, b_new = a_new + d;
+            // the four occupancies in one round trip; the positions may
+            // coincide (a_new == a_old, a_new == b_old, b_new == a_old), which
+            // the energy change and the final counts account for in registers
+            const int o1 = occ[a_old], o2 = occ[b_old], o3 = occ[a_new], o4 = occ[b_new];
+            const int c3 = o3 - (a_new == a_old) - (a_new == b_old);  // after removing pair k
+            const int c4 = o4 - (b_new == a_old) - (b_new == b_old);
+            const int de = (o1 == 1) + (o2 == 1) - (c3 == 0) - (c4 == 0);
             const bool acc = de <= 0 || r[2] < (de == 1 ? T1 : T2);
             if (acc) {
+                // final counts of the (possibly repeated) four positions; a
+                // repeated position receives the same value from every write
+                occ[a_old] = (uint8_t)(o1 - 1 + (a_old == a_new) + (a_old == b_new));
+                occ[b_old] = (uint8_t)(o2 - 1 + (b_old == a_new) + (b_old == b_new));
+                occ[a_new] = (uint8_t)(c3 + 1);
+                occ[b_new] = (uint8_t)(c4 + 1);
                 s[k] = (uint8_t)a_new;
                 E += de;
                 ++mv_acc;
-            } else {
-                occ[a_new]--;
-                occ[a_new + d]--;
-                occ[a_old]++;
-                occ[a_old + d]++;
             }
         }
         // 3. exchange (j, j+1) with j of the iteration's parity
         const int parity = (int)(it & 1);
-        const int E_up = __shfl_down(E, 1, 64);
-        const int slot_up = __shfl_down(slot, 1, 64);
+        const int E_up = from_lane_above(E);
+        const int slot_up = from_lane_above(slot);
         const bool lower = live && lane + 1 < M && (lane & 1) == parity;
         bool sw = false;
         if (lower) {
             const int de = E - E_up;
-            sw = de <= 0 || r[3] < a.swap_thr[lane * H + de];
+            sw = de <= 0 || r[3] < swap_thr[lane * H + de];
         }
-        const int sw_from_below = __shfl_up((int)sw, 1, 64);
-        const int E_dn = __shfl_up(E, 1, 64);
-        const int slot_dn = __shfl_up(slot, 1, 64);
+        const int sw_from_below = from_lane_below((int)sw);
+        const int E_dn = from_lane_below(E);
+        const int slot_dn = from_lane_below(slot);
         const bool upper = live && lane >= 1 && ((lane - 1) & 1) == parity && sw_from_below;
         if (sw) {
             E = E_up;

@@ -172,10 +172,14 @@ static sk_status pt_run_impl(const Relaxed& R, const sk_pt_params* p, hipStream_
         if (j + 1 < M)
             for (int e = 1; e < H; ++e) stt[(size_t)j * H + e] = accept_threshold(p->beta[j + 1] - p->beta[j], e);
     }
+    // host sources of queued copies are declared before D, whose destructor
+    // (hipFree) waits for the device, so they outlive every copy on any path
+    const std::vector<float> beta_f(p->beta, p->beta + M);
     PtDevice D;
     const size_t nst = (size_t)Lad * M * n, nh = (size_t)Lad * M * H, nl = (size_t)Lad * M;
     const int slot_bytes = (n + H + 3) & ~3;
-    const size_t lds = (size_t)64 * slot_bytes + (size_t)M * H * sizeof(uint32_t);
+    // LDS: 64 configuration slots, the histograms and the exchange thresholds
+    const size_t lds = (size_t)64 * slot_bytes + 2 * (size_t)M * H * sizeof(uint32_t);
     // iterations per launch; LDS counters stay below 2^32
     const uint64_t seg = (p->segment > 0 && p->segment <= (1ull << 30)) ? p->segment : (1ull << 24);
     PT_HIP(hipMalloc(&D.mt, mt.size() * sizeof(uint32_t)));
@@ -224,7 +228,7 @@ static sk_status pt_run_impl(const Relaxed& R, const sk_pt_params* p, hipStream_
     if (learned) {
         MlpGeo g;
         if (!mlp_geometry(n, R.variant, g)) return SK_EINVAL;
-        PT_OK(net.init(g, L->hidden1, L->hidden2));
+        PT_OK(net.init(g, L->hidden1, L->hidden2, stream));
         if (L->params) {
             PT_HIP(hipMemcpyAsync(net.P, L->params, net.count * sizeof(float), hipMemcpyHostToDevice, stream));
         } else {
@@ -233,10 +237,9 @@ static sk_status pt_run_impl(const Relaxed& R, const sk_pt_params* p, hipStream_
             PT_HIP(hipMemcpyAsync(net.P, init.data(), net.count * sizeof(float), hipMemcpyHostToDevice, stream));
             PT_HIP(hipStreamSynchronize(stream));
         }
-        std::vector<float> bf(p->beta, p->beta + M);
         PT_HIP(hipMalloc(&D.beta_f, M * sizeof(float)));
         PT_HIP(hipMalloc(&D.la, nl * sizeof(uint64_t)));
-        PT_HIP(hipMemcpyAsync(D.beta_f, bf.data(), M * sizeof(float), hipMemcpyHostToDevice, stream));
+        PT_HIP(hipMemcpyAsync(D.beta_f, beta_f.data(), M * sizeof(float), hipMemcpyHostToDevice, stream));
         PT_HIP(hipMemsetAsync(D.la, 0, nl * sizeof(uint64_t), stream));
         if (L->train_steps > 0) {
             // training pool: the learned levels' configurations at each snapshot

@@ -39,7 +39,8 @@ struct MlpNet {
     ~MlpNet();
     void release();
     void free_batch();
-    sk_status init(const MlpGeo& geo, int h1, int h2);
+    // allocates parameters, gradient and Adam moments (moments zeroed on s)
+    sk_status init(const MlpGeo& geo, int h1, int h2, hipStream_t s);
     sk_status reserve(int B);
     sk_status set_betas(const double* betas, int B, hipStream_t s);
     sk_status forward(const float* Xin, float* Zout, int B, hipStream_t s);
