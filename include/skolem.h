@@ -65,7 +65,10 @@ typedef enum {
                                (Lemma 2.4; for every variant this holds exactly when the
                                existence conditions do), only the half with the highest
                                chunk variable (an even position) at +1 is evaluated and
-                               the sum is doubled */
+                               the sum is doubled; and for Skolem and Langford pairings
+                               the reversal symmetry (Lemma 2.3) weights the settings of
+                               the middle job variables by 0, 1 or 2 so that about half
+                               of the remaining work is skipped (sk_stats.reversal_quads) */
 
 /* Unsigned 128-bit integer; every count with n <= 32 fits. */
 typedef struct { uint64_t lo, hi; } sk_u128;
@@ -108,6 +111,7 @@ typedef struct {
     double ms_per_launch_avg;
     uint64_t primes[8];
     int symmetry_halved;     /* 1 if the Lemma 2.4 half was evaluated and doubled */
+    int reversal_quads;      /* reversal weighting (Lemma 2.3): quadruples in use, 0 if none */
 } sk_stats;
 
 /* Progress callback: return nonzero to abort (the call then returns SK_EABORTED). */
@@ -379,6 +383,8 @@ typedef struct {
     int slot_factor[32]; /* factor index k-1 in each slot, -1 for a constant-1 slot */
     int symmetric;    /* 1 if the term is invariant under negating the even positions
                          (Lemma 2.4), so sk_count evaluates half the sign vectors */
+    int reversal_quads; /* reversal (Lemma 2.3) quadruples sk_count uses with the tuned
+                           kernel; it then evaluates 1/2 + 2^-(r+1) of the remaining jobs */
 } sk_plan_desc;
 
 sk_status sk_describe(int n, int variant, sk_plan_desc *out);

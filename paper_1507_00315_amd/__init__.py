@@ -55,7 +55,7 @@ class Stats(ctypes.Structure):
                 ("chunks", ctypes.c_uint64), ("nprimes", ctypes.c_int), ("passes", ctypes.c_int),
                 ("log2_chunk_terms", ctypes.c_int), ("kernel_variant", ctypes.c_int),
                 ("ms_per_launch_avg", ctypes.c_double), ("primes", ctypes.c_uint64 * 8),
-                ("symmetry_halved", ctypes.c_int)]
+                ("symmetry_halved", ctypes.c_int), ("reversal_quads", ctypes.c_int)]
 
     def as_dict(self) -> Dict:
         d = {name: getattr(self, name) for name, _ in self._fields_ if name != "primes"}
@@ -71,7 +71,7 @@ class PlanDesc(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("n_lane", ctypes.c_int), ("n_walk", ctypes.c_int),
                 ("n_job", ctypes.c_int), ("quads", ctypes.c_int), ("groups", ctypes.c_int),
                 ("halved", ctypes.c_int), ("primes", ctypes.c_int), ("slot_factor", ctypes.c_int * 32),
-                ("symmetric", ctypes.c_int)]
+                ("symmetric", ctypes.c_int), ("reversal_quads", ctypes.c_int)]
 
 
 class LearnedParams(ctypes.Structure):

@@ -24,7 +24,7 @@ __device__ __forceinline__ void batch_case(uint64_t chunk, const BatchInstance& 
         pr[i] = in.prime[i];
         pinv[i] = in.pinv[i];
     }
-    exact_v2_chunk<V, N, P, kBatchInner>(chunk, in.jb, pr, pinv, res);
+    exact_v2_chunk<V, N, P, kBatchInner>(chunk, in.jb, in.rev, pr, pinv, res);
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int i = 0; i < P; ++i) out_row[i] = res[i];

@@ -343,8 +343,8 @@ struct ExactV2 {
 // One chunk (chunk id, 2^jb jobs) evaluated by the calling wavefront.
 // Returns in every lane the wave's residues (balanced, exact fp64 integers).
 template <int V, int N, int P, int INNER>
-__device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const double (&pr)[P], const double (&pinv)[P],
-                                               double (&res)[P])
+__device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const RevMasks& rev, const double (&pr)[P],
+                                               const double (&pinv)[P], double (&res)[P])
 {
     using K = ExactV2<V, N, P, INNER>;
     constexpr PlanCE PL = K::PL;
@@ -370,8 +370,20 @@ __device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const dou
     const uint64_t njobs = 1ull << jb;
     const uint64_t xu_chunk = chunk << (1 + W + jb);
     for (uint64_t j = 0; j < njobs; ++j) {
+        const uint64_t xu_job = xu_chunk | (j << (1 + W));
+        // reversal weight of this job (wave-uniform: job variables only)
+        int w = 1;
+        for (int q = 0; q < rev.r; ++q) {
+            const int pu = __builtin_popcountll(xu_job & rev.u[q]) & 1;  // 0: u = +1
+            const int pv = __builtin_popcountll(xu_job & rev.v[q]) & 1;
+            if (pu != pv) {
+                w = pu == 0 ? 2 : 0;
+                break;
+            }
+        }
+        if (w == 0) continue;
         typename K::Uniform u;
-        u.XU = xu_chunk | (j << (1 + W));
+        u.XU = xu_job;
         K::init_uniform(u);
         // per-lane part A of every slot (pairs touching a lane variable)
         uint32_t A[NP];
@@ -423,7 +435,8 @@ __device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const dou
         }
         static_for<0, P>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            acc_tot[i] = reduce_balanced(neg0 ? acc_tot[i] - acc[i] : acc_tot[i] + acc[i], pr[i], pinv[i]);
+            const double aw = w == 2 ? acc[i] + acc[i] : acc[i];  // |aw| <= 1.5 p
+            acc_tot[i] = reduce_balanced(neg0 ? acc_tot[i] - aw : acc_tot[i] + aw, pr[i], pinv[i]);
         });
     }
     static_for<0, P>([&](auto ic) {
@@ -450,7 +463,7 @@ __global__ void __launch_bounds__(256) exact_v2_kernel(const ExactArgsV2 a, doub
         pr[i] = a.prime[i];
         pinv[i] = a.pinv[i];
     }
-    exact_v2_chunk<V, N, P, INNER>(chunk, a.job_bits_per_chunk, pr, pinv, res);
+    exact_v2_chunk<V, N, P, INNER>(chunk, a.job_bits_per_chunk, a.rev, pr, pinv, res);
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int i = 0; i < P; ++i) out[wave * P + i] = res[i];

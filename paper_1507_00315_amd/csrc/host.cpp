@@ -206,6 +206,43 @@ static bool hat_symmetric(const Plan& P)
     return e % 2 == 0;
 }
 
+// Reversal quadruples (Lemma 2.3; see RevMasks): odd positions j whose mirror
+// 2n+1-j is also a job variable, the highest job variable (the one the Lemma
+// 2.4 half fixes) excluded, taken nearest the middle first, two per quadruple.
+// Skolem and Langford only (the hooked position set is not symmetric).
+static RevMasks reversal_masks(const Plan& P)
+{
+    RevMasks rv;
+    std::memset(&rv, 0, sizeof(rv));
+    if (P.variant == SK_HOOKED) return rv;
+    const int lo = P.n_walk + 1, hi = P.n_walk + P.n_job;  // job ranks
+    const int top = 2 * P.n;                                // positions 1..2n, rank = position - 1
+    std::vector<int> js;
+    for (int rank = lo; rank < hi; ++rank) {
+        const int j = P.pos[rank];
+        const int jm = top + 1 - j;
+        if (j % 2 == 0) continue;  // each mirror pair has exactly one odd member
+        const int rm = jm - 1;
+        if (rm < lo || rm >= hi) continue;
+        js.push_back(j);
+    }
+    std::sort(js.begin(), js.end(), [&](int a, int b) { return std::abs(2 * a - top - 1) < std::abs(2 * b - top - 1); });
+    rv.r = std::min<int>(kRevMax, (int)js.size() / 2);
+    for (int q = 0; q < rv.r; ++q) {
+        const int j1 = js[2 * q], j2 = js[2 * q + 1];
+        rv.u[q] = (1ull << (j1 - 1)) | (1ull << (j2 - 1));
+        rv.v[q] = (1ull << (top - j1)) | (1ull << (top - j2));
+    }
+    return rv;
+}
+
+// Sign vectors evaluated out of `total` when r reversal quadruples are in use:
+// weight-0 jobs are 1/4 + 1/8 + ... + 1/2^(r+1) of all jobs.
+static uint64_t reversal_evaluated(uint64_t total, int r)
+{
+    return r == 0 ? total : (total >> (r + 1)) * ((1ull << r) + 1);
+}
+
 static sk_status make_plan(int n, int variant, Plan& P)
 {
     if (variant < 0 || variant > 2) return SK_EINVAL;
@@ -287,6 +324,8 @@ struct SumRequest {
     // total mode: evaluate only the chunks whose highest chunk variable (an
     // even position) is +1, and double (valid when hat_symmetric)
     bool half = false;
+    // total mode, tuned kernel: reversal weights (Lemma 2.3)
+    bool reverse = false;
 };
 
 // ------------------------------------------------------------------ kernels
@@ -371,6 +410,8 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
     }
     const bool half = !listed && R.half && nchunks >= 2;
     if (half) nchunks >>= 1;
+    const RevMasks rev = (!listed && R.reverse && kv == 2) ? reversal_masks(P) : RevMasks{};
+    const int rev_r = rev.r;
     const uint64_t terms_per_chunk = 1ull << (P.n_lane + P.n_walk + jb);
     const int nbatches = (np + batch - 1) / batch;
     const uint64_t terms_total = nchunks * terms_per_chunk * (uint64_t)nbatches;
@@ -432,6 +473,7 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
                 a2.pinv[i] = 1.0 / (double)bp[i];
             }
             a2.job_bits_per_chunk = jb;
+            if (rev_r > 0) a2.rev = rev;
         }
         for (uint64_t base = 0; base < nchunks; base += wpl) {
             const uint64_t nw = std::min<uint64_t>(wpl, nchunks - base);
@@ -480,7 +522,8 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
     }
     if (half)
         for (int i = 0; i < np; ++i) out[i] = (uint64_t)(((u128)out[i] * 2) % R.primes[i]);
-    st.terms += nchunks * terms_per_chunk;
+    st.terms += reversal_evaluated(nchunks * terms_per_chunk, rev_r);
+    st.reversal_quads = rev_r;
     st.chunks += nchunks;
     st.log2_chunk_terms = P.n_lane + P.n_walk + jb;
     st.kernel_variant = kv;
@@ -553,6 +596,7 @@ struct BatchJob {
     std::vector<uint64_t> res;     // out: kernel-sum residues
     uint64_t terms = 0;
     bool half = false;             // Lemma 2.4 half (see SumRequest::half)
+    bool reverse = false;          // reversal weights (see SumRequest::reverse)
 };
 
 // One persistent launch over the chunks of every job.  probe_shift > 0 runs
@@ -582,6 +626,7 @@ static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t
         jb = std::max(0, std::min(jb, P.n_job));
         a.inst[b].kind = kind;
         a.inst[b].jb = jb;
+        if (jobs[b].reverse) a.inst[b].rev = reversal_masks(P);
         for (size_t i = 0; i < jobs[b].primes.size(); ++i) {
             a.inst[b].prime[i] = (double)jobs[b].primes[i];
             a.inst[b].pinv[i] = 1.0 / (double)jobs[b].primes[i];
@@ -591,7 +636,8 @@ static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t
         if (jobs[b].half) total >>= 1;
         uint64_t use = std::max<uint64_t>(1, total >> probe_shift);
         nch[b] = use;
-        jobs[b].terms = use << (P.n_lane + P.n_walk + jb);
+        jobs[b].terms = reversal_evaluated(use << (P.n_lane + P.n_walk + jb), a.inst[b].rev.r);
+        st.reversal_quads = std::max(st.reversal_quads, (int)a.inst[b].rev.r);
     }
     std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
         return (jobs[x].terms / nch[x]) > (jobs[y].terms / nch[y]);
@@ -809,6 +855,7 @@ static sk_status count_impl(int n, int variant, unsigned flags, const sk_tuning*
             R.progress = progress;
             R.progress_ctx = pctx;
             R.half = !(flags & SK_NO_SYMMETRY) && hat_symmetric(P);
+            R.reverse = !(flags & SK_NO_SYMMETRY);
             std::vector<uint64_t> res;
             s = run_sum(R, res, st);
             if (s != SK_OK) return s;
@@ -907,6 +954,7 @@ sk_status sk_count_batch(const sk_instance* inst, size_t k, const sk_tuning* tun
                 BatchJob j;
                 j.plan = &plans[i];
                 j.half = !(inst[i].flags & SK_NO_SYMMETRY) && hat_symmetric(plans[i]);
+                j.reverse = !(inst[i].flags & SK_NO_SYMMETRY);
                 const int np = primes_for(plans[i].n);
                 j.primes = default_primes(np, pass * np);
                 jobs.push_back(j);
@@ -1032,6 +1080,7 @@ sk_status sk_describe(int n, int variant, sk_plan_desc* out)
     out->primes = primes_needed(n);
     for (int i = 0; i < 32; ++i) out->slot_factor[i] = (i < 4 * P.nq) ? P.slot[i].pad : -1;
     out->symmetric = hat_symmetric(P) ? 1 : 0;
+    out->reversal_quads = reversal_masks(P).r;
     return SK_OK;
 }
 

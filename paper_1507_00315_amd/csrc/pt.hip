@@ -32,13 +32,12 @@ namespace sk {
 
 // Placement index -> left position of pair k (1-based), for the variant's
 // position set.
+// (written as selects, so that the move stays one basic block)
 __device__ __forceinline__ int placement(const PtArgs& a, int d, int idx)
 {
-    if (a.variant == 2) {  // hooked: 1..2n-1 and 2n+1
-        const int inside = 2 * a.n - 1 - d;  // placements with both ends <= 2n-1
-        return idx < inside ? 1 + idx : 2 * a.n + 1 - d;
-    }
-    return 1 + idx;
+    // hooked: 1..2n-1 and 2n+1; the first 2n-1-d placements end at or below
+    // 2n-1, the last one ends at 2n+1
+    return (a.variant == 2 && idx >= 2 * a.n - 1 - d) ? 2 * a.n + 1 - d : 1 + idx;
 }
 
 // The value held by lane + 1 / lane - 1 (wavefront shifts by one lane, DPP;
@@ -53,12 +52,11 @@ __device__ __forceinline__ int from_lane_below(int x)
     return __builtin_amdgcn_update_dpp(x, x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
 }
 
-__device__ __forceinline__ int pair_diff(const PtArgs& a, int k) { return a.variant == 1 ? k + 2 : k + 1; }
+__device__ __forceinline__ int pair_diff(const PtArgs& a, int k) { return k + 1 + (a.variant == 1); }
 
 __device__ __forceinline__ int placements_of(const PtArgs& a, int d)
 {
-    if (a.variant == 2) return d == 1 ? 2 * a.n - 2 : 2 * a.n - d;
-    return 2 * a.n - d;
+    return 2 * a.n - d - (a.variant == 2 && d == 1);
 }
 
 __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
@@ -117,12 +115,16 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     }
     __syncthreads();
 
+    // The words of iteration it + 1 are drawn during iteration it (they depend
+    // on nothing the iteration computes), so their arithmetic fills the wait
+    // for the iteration's first LDS read.
+    uint32_t rn[4];
+    philox4x32_10((uint32_t)a.it_begin, (uint32_t)(a.it_begin >> 32), ladder, (uint32_t)lane, k0, k1, rn);
     for (uint64_t it = a.it_begin; it < a.it_end; ++it) {
         // 1. record (LDS atomic add: no read-back, each lane owns its row)
         if (live) atomicAdd(&hist[lane * H + E], 1u);
         // 2. move
-        uint32_t r[4];
-        philox4x32_10((uint32_t)it, (uint32_t)(it >> 32), ladder, (uint32_t)lane, k0, k1, r);
+        const uint32_t r[4] = {rn[0], rn[1], rn[2], rn[3]};
         if (live) {
             uint8_t* s = slots + (size_t)slot * slot_bytes;
             uint8_t* occ = s + n;
@@ -131,6 +133,11 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
             const int idx = (int)__umulhi(r[1], (uint32_t)placements_of(a, d));
             const int a_new = placement(a, d, idx);
             const int a_old = s[k];
+            // next iteration's words while the read of s[k] is in flight (the
+            // lanes above the top level never use theirs); the scheduling
+            // barrier keeps the read issued ahead of them
+            __builtin_amdgcn_sched_barrier(0);
+            philox4x32_10((uint32_t)(it + 1), (uint32_t)((it + 1) >> 32), ladder, (uint32_t)lane, k0, k1, rn);
             const int b_old = a_old + d, b_new = a_new + d;
             // the four occupancies in one round trip; the positions may
             // coincide (a_new == a_old, a_new == b_old, b_new == a_old), which
@@ -140,17 +147,18 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
             const int c4 = o4 - (b_new == a_old) - (b_new == b_old);
             const int de = (o1 == 1) + (o2 == 1) - (c3 == 0) - (c4 == 0);
             const bool acc = de <= 0 || r[2] < (de == 1 ? T1 : T2);
-            if (acc) {
-                // final counts of the (possibly repeated) four positions; a
-                // repeated position receives the same value from every write
-                occ[a_old] = (uint8_t)(o1 - 1 + (a_old == a_new) + (a_old == b_new));
-                occ[b_old] = (uint8_t)(o2 - 1 + (b_old == a_new) + (b_old == b_new));
-                occ[a_new] = (uint8_t)(c3 + 1);
-                occ[b_new] = (uint8_t)(c4 + 1);
-                s[k] = (uint8_t)a_new;
-                E += de;
-                ++mv_acc;
-            }
+            // final counts of the (possibly repeated) four positions, written
+            // whether or not the move is accepted (a rejected move writes back
+            // what it read); a repeated position receives the same value from
+            // every write
+            const int ac = acc ? 1 : 0;
+            occ[a_old] = (uint8_t)(o1 + ac * ((a_old == a_new) + (a_old == b_new) - 1));
+            occ[b_old] = (uint8_t)(o2 + ac * ((b_old == a_new) + (b_old == b_new) - 1));
+            occ[a_new] = (uint8_t)(acc ? c3 + 1 : o3);
+            occ[b_new] = (uint8_t)(acc ? c4 + 1 : o4);
+            s[k] = (uint8_t)(acc ? a_new : a_old);
+            E += ac * de;
+            mv_acc += ac;
         }
         // 3. exchange (j, j+1) with j of the iteration's parity
         const int parity = (int)(it & 1);

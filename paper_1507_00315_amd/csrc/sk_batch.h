@@ -26,6 +26,7 @@ constexpr int kBatchMaxInstances = 16;
 constexpr int kBatchChunkBits = 48;  // item = (instance << 48) | chunk id
 
 struct BatchInstance {
+    RevMasks rev;  // reversal weights of the instance (r = 0: none)
     int32_t kind;  // case of SK_BATCH_CASES
     int32_t jb;    // job bits enumerated inside one chunk
     double prime[kMaxPrimes];

@@ -50,9 +50,28 @@ struct ExactArgs {
     int32_t qb[5];               // product group g covers quads [qb[g], qb[g+1])
 };
 
+// Reversal weights (Lemma 2.3).  For Skolem and Langford pairings the term
+// at x equals the term at the reversed vector, mapped back to x_1 = +1 by a
+// global negation: x'_i = x_2n x_(2n+1-i).  For odd positions j1, j2 whose
+// mirrors 2n+1-j1, 2n+1-j2 (even) are also job variables, the products
+//     u = x_j1 x_j2,   v = x_(2n+1-j1) x_(2n+1-j2)
+// swap under that map (the x_2n factors cancel) and are unchanged by the
+// negation of the even positions (Lemma 2.4).  A job (wave-uniform setting of
+// the job variables) gets weight 2 if, at the first quadruple with u != v,
+// u = +1, weight 0 if u = -1 there (the partner job carries it), and weight 1
+// if u = v for every quadruple.  Jobs of weight 0 are skipped.
+constexpr int kRevMax = 4;
+struct RevMasks {
+    uint64_t u[kRevMax];  // bits j1-1, j2-1
+    uint64_t v[kRevMax];  // bits of the mirrors
+    int32_t r;            // quadruples in use (0: no reversal weighting)
+    int32_t pad;
+};
+
 // Arguments of one launch of the specialised exact kernel (exact_v2.hip);
 // everything about the instance itself is compiled in.
 struct ExactArgsV2 {
+    RevMasks rev;
     double prime[kMaxPrimes];
     double pinv[kMaxPrimes];
     int32_t job_bits_per_chunk;  // low job variables enumerated inside one chunk

@@ -95,3 +95,12 @@ def test_prime_count_covers_the_count_bound():
             bound = math.factorial(n) << 8
             assert math.prod(primes[:k]) > bound, (v, n, k)
             assert k == 1 or math.prod(primes[:k - 1]) <= bound, (v, n, k)
+
+
+def test_reversal_quadruples_for_skolem_and_langford_only():
+    # Lemma 2.3 needs a position set symmetric under i -> 2n + 1 - i
+    for n in range(12, 33):
+        assert sk.describe(n, "skolem")["reversal_quads"] >= 2
+        assert sk.describe(n, "langford")["reversal_quads"] >= 2
+        if n <= 31:
+            assert sk.describe(n, "hooked")["reversal_quads"] == 0

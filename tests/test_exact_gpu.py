@@ -55,9 +55,12 @@ def test_config1_skolem_12_and_zeros():
     r = sk.count_ex(12, "skolem", tuning={"primes": 2}, no_symmetry=True)
     assert r.count == 227968
     assert r.stats["nprimes"] == 2 and r.stats["terms"] == 1 << 23 and r.stats["symmetry_halved"] == 0
-    # by default only the Lemma 2.4 half is evaluated
+    # by default only the Lemma 2.4 half is evaluated, of which the reversal
+    # weights (Lemma 2.3) keep 1/2 + 2^-(r+1)
     h = sk.count_ex(12, "skolem", tuning={"primes": 2})
-    assert h.count == 227968 and h.stats["terms"] == 1 << 22 and h.stats["symmetry_halved"] == 1
+    r = h.stats["reversal_quads"]
+    assert h.count == 227968 and h.stats["symmetry_halved"] == 1 and r >= 1
+    assert h.stats["terms"] == (1 << 22) // 2 ** (r + 1) * (2 ** r + 1)
     for n in (10, 11):
         assert sk.count(n, "skolem", no_shortcut=True) == 0
     assert O.is_valid_pairing(O.skolem_construction(12), 12, "skolem")
@@ -244,11 +247,13 @@ def test_l28_slice_chunks_match_cpu_recomputation():
     assert [r[0] for r in rows] == [c["residue"] for c in g["chunks"]]
 
 
-@pytest.mark.parametrize("variant,n", [("skolem", 13), ("langford", 12), ("hooked", 11), ("skolem", 16)])
-def test_lemma_2_4_half_equals_full_sum(variant, n):
+@pytest.mark.parametrize("variant,n", [("skolem", 13), ("langford", 12), ("hooked", 11), ("skolem", 16),
+                                       ("langford", 19), ("skolem", 17)])
+def test_symmetry_reductions_equal_full_sum(variant, n):
     """The default count evaluates the half of the sign vectors with the top
-    chunk variable (an even position) at +1 and doubles it; the full sum must
-    give the same count, with twice the sign vectors evaluated."""
+    chunk variable (an even position) at +1 and doubles it (Lemma 2.4), and for
+    Skolem and Langford weights the middle job variables by reversal (Lemma
+    2.3); the full sum must give the same count."""
     _say("symmetry", variant, n)
     a = sk.count_ex(n, variant, ordered=True)
     b = sk.count_ex(n, variant, ordered=True, no_symmetry=True)
@@ -256,4 +261,10 @@ def test_lemma_2_4_half_equals_full_sum(variant, n):
     if n <= 13:
         assert a.count == O.count_backtrack(n, variant, threads=8)
     assert a.stats["symmetry_halved"] == 1 and b.stats["symmetry_halved"] == 0
-    assert 2 * a.stats["terms"] == b.stats["terms"]
+    r = a.stats["reversal_quads"]
+    if variant == "hooked" or a.stats["kernel_variant"] != 2:
+        assert r == 0  # no reversal symmetry of the hooked position set; the reference body has no weights
+    else:
+        assert r == sk.describe(n, variant)["reversal_quads"] >= 1
+    # evaluated: the Lemma 2.4 half, of which reversal keeps 1/2 + 2^-(r+1)
+    assert a.stats["terms"] * 2 ** (r + 1) == b.stats["terms"] // 2 * (2 ** r + 1)

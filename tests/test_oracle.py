@@ -207,6 +207,30 @@ def test_even_position_symmetry_lemma_2_4(variant):
         assert b == (a if eps == 1 else (-a) % p), (variant, n)
 
 
+@pytest.mark.parametrize("variant", ["skolem", "langford"])
+def test_reversal_symmetry_lemma_2_3(variant):
+    """Reversal x_i -> x_(2n+1-i) leaves prod x and F unchanged (Lemma 2.3);
+    followed by a global negation when x_2n = -1 (Lemma 2.2) it keeps x_1 =
+    +1.  So the partial sum with x_1 = +1, x_2n = s and x_q = s_q fixed equals
+    the one with x_2n = s and x_(2n+1-q) = s * s_q fixed -- the identity the
+    reversal weights of the exact count rely on."""
+    rng = random.Random(23)
+    p = P3[2]
+    for n in range(4, 10):
+        pos, _ = O.instance(n, variant)
+        top = 2 * n
+        for _ in range(3):
+            s_top = rng.choice((1, -1))
+            inner = rng.sample(range(2, top), 4)
+            fixed = {1: 1, top: s_top}
+            fixed.update({q: rng.choice((1, -1)) for q in inner})
+            image = {1: 1, top: s_top}
+            image.update({top + 1 - q: s_top * v for q, v in fixed.items() if q not in (1, top)})
+            a = O.chunk_partial(n, variant, fixed, p, "gray", 2)
+            b = O.chunk_partial(n, variant, image, p, "gray", 2)
+            assert a == b, (variant, n, fixed, image)
+
+
 def test_primes():
     assert O.is_prime(2 ** 61 - 1) and O.is_prime(2 ** 31 - 1)
     assert not O.is_prime(2 ** 61 + 1) and not O.is_prime(561) and not O.is_prime(3215031751)
