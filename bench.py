@@ -354,8 +354,13 @@ def main():
         d = sk.describe(n, v)
         d["primes_used"] = d["primes"]
         instr_per = valu_per_term(d)
-        # sign vectors the kernel evaluates (half of 2^(2n-1) where Lemma 2.4 applies)
-        terms_inst = terms_per_step if slice_ids is not None else (1 << (2 * n - 1)) >> d["symmetric"]
+        # sign vectors the kernel evaluates: half of 2^(2n-1) where Lemma 2.4
+        # applies, and of those 1/2 + 2^-(r+1) with r reversal quadruples
+        if slice_ids is not None:
+            terms_inst = terms_per_step
+        else:
+            r = d["reversal_quads"] if stats_of(results[0])[0]["reversal_quads"] else 0
+            terms_inst = ((1 << (2 * n - 1)) >> d["symmetric"]) // 2 ** (r + 1) * (2 ** r + 1)
         instr += terms_inst * instr_per
         ring += terms_inst * ring_ops_per_term(n, d["primes"])
     kms = sum(s["kernel_ms"] for st in results for s in stats_of(st)) / args.steps
@@ -364,6 +369,7 @@ def main():
     kernel_name = sk.kernel_name(stats_of(results[0])[0]["kernel_variant"])
     instr_per_term = instr / terms_per_step
 
+    covered = terms_per_step if slice_ids is not None else sum(1 << (2 * n - 1) for v, n in instances)
     line = {
         "metric": METRIC,
         "value": value,
@@ -383,8 +389,9 @@ def main():
                    "primes_per_instance": {f"{v}:{n}": sk.describe(n, v)["primes"] for v, n in instances},
                    "log2_chunk_terms": stats_of(results[0])[0]["log2_chunk_terms"],
                    "lemma_2_4_halving": bool(stats_of(results[0])[0].get("symmetry_halved")),
-                   "sign_vectors_covered_per_step": (terms_per_step if slice_ids is not None else
-                                                     sum(1 << (2 * n - 1) for v, n in instances)),
+                   "sign_vectors_covered_per_step": covered,
+                   "sign_vectors_covered_per_s": covered * args.steps / elapsed,
+                   "reversal_quads": stats_of(results[0])[0].get("reversal_quads", 0),
                    "results_match_expected": all_ok},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "VALU lane-instr/s",
                      "frac": achieved / PEAK_LANE_OPS, "traffic": traffic_per_launch(kernel_name, args.workload,
