@@ -140,9 +140,10 @@ sk_status sk_count_ex(int n, int variant, unsigned flags, const sk_tuning *tune,
  * sk_count_batch -- exact counts of k instances (Sec. 2) in one persistent
  * kernel launch: wavefronts pull (instance, chunk) work items from one global
  * queue, so instances of very different size share the GPU without a tail per
- * instance.  Instances whose kernel is not compiled into the batched launch
- * and instances with tune->kernel == 1 or a larger prime count
- * are counted by separate launches in the same call.
+ * instance.  The batched launch holds the tuned bodies of Skolem n = 16, 17,
+ * 20, 21, Langford n = 15, 16, 19, 20 and hooked n = 14, 15; other instances,
+ * and instances with tune->kernel == 1 or a larger prime count, are counted
+ * by separate launches in the same call.
  *   inst  : k instances (k >= 1); out: k counts, in order
  *   tune  : NULL = the shape found by sk_autotune_batch for this instance set
  *           (cached per GPU model), else log2_chunk_terms (sign vectors per work
