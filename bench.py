@@ -61,6 +61,7 @@ MEASURED_TRAFFIC = {
     # (kernel, workload, log2 sign vectors per work item, waves per launch):
     #     (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
     ("exact_batch_kernel", "batch", 24, 4096): ("91f52758abca7754", 3208.4375, 10651.4375),
+    ("exact_v2_kernel", "s20", 25, 0): ("6ea75459c3900ab8", 1574.8125, 6272.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
