@@ -137,6 +137,29 @@ sk_status sk_count_ex(int n, int variant, unsigned flags, const sk_tuning *tune,
                       sk_stats *stats, sk_u128 *out);
 
 /*
+ * sk_count_part / sk_count_combine -- one count split into independent jobs
+ * (Sec. 2.2: the sign space is split, the parts run on different GPUs, and the
+ * results are put together at the end).  sk_count_part evaluates the part-th
+ * of `parts` equal shares of the work sk_count would do for (n, variant,
+ * flags) and returns its sum modulo each of the count's primes (the
+ * sk_describe(n, variant).primes largest primes below 2^46), Lemma 2.4
+ * doubling and reversal weights included; separate calls (processes, GPUs,
+ * machines) may compute the parts.  sk_count_combine (host only) adds the
+ * parts' residues and finishes the count exactly as sk_count does (CRT, bound
+ * check, reflections).
+ *   parts    : a power of two, at most the number of chunks of the count
+ *              (SK_EINVAL otherwise); part < parts
+ *   residues : sk_count_part: sk_describe(...).primes outputs in [0, p);
+ *              sk_count_combine: parts x primes, row k from part k
+ * SK_VERIFY is not accepted by sk_count_part.  Errors: as sk_count.
+ */
+sk_status sk_count_part(int n, int variant, unsigned flags, uint64_t part, uint64_t parts,
+                        const sk_tuning *tune, void *stream, sk_progress_fn progress,
+                        void *progress_ctx, sk_stats *stats, uint64_t *residues);
+sk_status sk_count_combine(int n, int variant, unsigned flags, const uint64_t *residues, uint64_t parts,
+                           sk_u128 *out);
+
+/*
  * sk_count_batch -- exact counts of k instances (Sec. 2) in one persistent
  * kernel launch: wavefronts pull (instance, chunk) work items from one global
  * queue, so instances of very different size share the GPU without a tail per

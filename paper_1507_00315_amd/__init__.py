@@ -130,6 +130,9 @@ def lib() -> ctypes.CDLL:
                                     u64p]
     L.sk_max_chunk_bits.argtypes = [c_int, c_int]
     L.sk_last_stats.argtypes = [ctypes.POINTER(Stats)]
+    L.sk_count_part.argtypes = [c_int, c_int, c_uint, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(Tuning), vp,
+                                PROGRESS_FN, vp, ctypes.POINTER(Stats), u64p]
+    L.sk_count_combine.argtypes = [c_int, c_int, c_uint, u64p, ctypes.c_uint64, ctypes.POINTER(U128)]
     L.sk_describe.argtypes = [c_int, c_int, ctypes.POINTER(PlanDesc)]
     L.sk_pt_bins.argtypes = [c_int, c_int]
     L.sk_pt_run.argtypes = [c_int, c_int, ctypes.POINTER(PtParams), vp, u64p, u64p, u64p,
@@ -160,7 +163,7 @@ def lib() -> ctypes.CDLL:
     L.sk_kernel_name.restype = ctypes.c_char_p
     for fn in ("sk_set_device", "sk_count", "sk_count_ex", "sk_sign_sum_residues", "sk_partial_chunks",
                "sk_max_chunk_bits", "sk_describe", "sk_count_batch", "sk_autotune_batch", "sk_pt_bins",
-               "sk_pt_run", "sk_approx", "sk_last_stats", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
+               "sk_pt_run", "sk_approx", "sk_last_stats", "sk_count_part", "sk_count_combine", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
                "sk_mlp_mh_step"):
         getattr(L, fn).restype = c_int
     _lib = L
@@ -170,7 +173,7 @@ def lib() -> ctypes.CDLL:
 EXPORTED = ["sk_set_device", "sk_count", "sk_count_ex", "sk_count_batch", "sk_autotune_batch", "sk_pt_bins",
             "sk_pt_run", "sk_approx", "sk_sign_sum_residues", "sk_partial_chunks",
             "sk_max_chunk_bits", "sk_describe", "sk_strerror", "sk_last_error", "sk_u128_to_decimal", "sk_kernel_name",
-            "sk_last_stats", "sk_mlp_param_count", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
+            "sk_last_stats", "sk_count_part", "sk_count_combine", "sk_mlp_param_count", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
             "sk_mlp_mh_step"]
 
 
@@ -244,6 +247,41 @@ def count(n: int, variant="skolem", ordered: bool = False, verify: bool = False,
     flags = _flags(ordered, verify, no_shortcut, no_symmetry)
     out = U128()
     _check(lib().sk_count(n, _variant(variant), flags, ctypes.byref(out)), f"sk_count(n={n})")
+    return out.value()
+
+
+def count_part(n: int, variant, part: int, parts: int, ordered: bool = False, no_shortcut: bool = False,
+               no_symmetry: bool = False, tuning: Optional[Dict] = None, stream=None,
+               progress: Optional[Callable[[int, int], Optional[bool]]] = None):
+    """Residues of the part-th of `parts` shares of an exact count (sk_count_part):
+    (residues, stats)."""
+    flags = _flags(ordered, False, no_shortcut, no_symmetry)
+    k = describe(n, variant)["primes"]
+    out = (ctypes.c_uint64 * k)()
+    st = Stats()
+    t = _tuning(tuning)
+
+    def _cb(_ctx, done, total):
+        if progress is None:
+            return 0
+        return 1 if progress(int(done), int(total)) else 0
+
+    cb = PROGRESS_FN(_cb)
+    _check(lib().sk_count_part(n, _variant(variant), flags, part, parts, ctypes.byref(t) if t else None,
+                               _stream_handle(stream), cb, None, ctypes.byref(st), out),
+           f"sk_count_part(n={n}, part={part}/{parts})")
+    return [int(x) for x in out], st.as_dict()
+
+
+def count_combine(n: int, variant, rows: Sequence[Sequence[int]], ordered: bool = False,
+                  no_shortcut: bool = False, no_symmetry: bool = False) -> int:
+    """The count from every part's residues (sk_count_combine, host only)."""
+    flags = _flags(ordered, False, no_shortcut, no_symmetry)
+    flat = [int(x) for row in rows for x in row]
+    arr = _u64_array(flat)
+    out = U128()
+    _check(lib().sk_count_combine(n, _variant(variant), flags, arr, len(rows), ctypes.byref(out)),
+           "sk_count_combine")
     return out.value()
 
 
@@ -508,6 +546,6 @@ def last_stats_dict(st: Stats) -> Dict:
 
 
 __all__ = ["count", "count_ex", "count_batch", "autotune_batch", "pt_run", "approx", "pt_bins", "sign_sum_residues",
-           "partial_chunks", "last_stats", "max_chunk_bits", "set_device", "mlp_param_count", "mlp_init", "mlp_forward",
+           "partial_chunks", "last_stats", "count_part", "count_combine", "max_chunk_bits", "set_device", "mlp_param_count", "mlp_init", "mlp_forward",
            "mlp_loss_grad", "mlp_train", "mlp_mh_step", "PROPOSAL_UNIFORM", "PROPOSAL_LEARNED",
            "SkolemError", "SKOLEM", "LANGFORD", "HOOKED", "lib", "EXPORTED"]

@@ -326,6 +326,9 @@ struct SumRequest {
     bool half = false;
     // total mode, tuned kernel: reversal weights (Lemma 2.3)
     bool reverse = false;
+    // total mode: only the part-th of `parts` equal, consecutive ranges of
+    // chunk indices (parts a power of two not above the chunk count)
+    uint64_t part = 0, parts = 1;
 };
 
 // ------------------------------------------------------------------ kernels
@@ -410,6 +413,16 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
     }
     const bool half = !listed && R.half && nchunks >= 2;
     if (half) nchunks >>= 1;
+    uint64_t chunk_offset = 0;
+    if (!listed && R.parts > 1) {
+        if ((R.parts & (R.parts - 1)) != 0 || R.part >= R.parts || R.parts > nchunks) {
+            g_last_error = "parts must be a power of two not above the number of chunks (" +
+                           std::to_string(nchunks) + "), part < parts";
+            return SK_EINVAL;
+        }
+        nchunks /= R.parts;
+        chunk_offset = R.part * nchunks;
+    }
     const RevMasks rev = (!listed && R.reverse && kv == 2) ? reversal_masks(P) : RevMasks{};
     const int rev_r = rev.r;
     const uint64_t terms_per_chunk = 1ull << (P.n_lane + P.n_walk + jb);
@@ -487,12 +500,12 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
             if ((e = hipEventRecord(e0, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
             if (kv == 1) {
                 a1.n_waves = nw;
-                a1.chunk_base = base;
+                a1.chunk_base = chunk_offset + base;
                 a1.chunk_ids = ids;
                 hipLaunchKernelGGL(fn1, dim3(blocks), dim3(256), 0, stream, a1, d_out);
             } else {
                 a2.n_waves = nw;
-                a2.chunk_base = base;
+                a2.chunk_base = chunk_offset + base;
                 a2.chunk_ids = ids;
                 hipLaunchKernelGGL(fn2, dim3(blocks), dim3(256), 0, stream, a2, d_out);
             }
@@ -881,6 +894,79 @@ static sk_status count_impl(int n, int variant, unsigned flags, const sk_tuning*
     st.ms_per_launch_avg = st.launches ? st.kernel_ms / (double)st.launches : 0.0;
     g_stats = st;
     if (stats_out) *stats_out = st;
+    return SK_OK;
+}
+
+sk_status sk_count_part(int n, int variant, unsigned flags, uint64_t part, uint64_t parts, const sk_tuning* tune,
+                        void* stream, sk_progress_fn progress, void* progress_ctx, sk_stats* stats_out,
+                        uint64_t* residues)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!residues || parts == 0 || part >= parts || (flags & SK_VERIFY)) return SK_EINVAL;
+    Plan P;
+    sk_status s = make_plan(n, variant, P);
+    if (s != SK_OK) return s;
+    const int np = primes_needed(n);
+    sk_stats st;
+    std::memset(&st, 0, sizeof(st));
+    std::vector<uint64_t> res(np, 0);
+    SumRequest R;
+    R.plan = &P;
+    R.primes = default_primes(np, 0);
+    if (existence(n, variant) || (flags & SK_NO_SHORTCUT)) {
+        R.log2_chunk_terms = (tune && tune->log2_chunk_terms > 0) ? tune->log2_chunk_terms : 0;
+        R.waves_per_launch = tune ? tune->waves_per_launch : 0;
+        R.kernel = tune ? tune->kernel : 0;
+        R.stream = (hipStream_t)stream;
+        R.progress = progress;
+        R.progress_ctx = progress_ctx;
+        R.half = !(flags & SK_NO_SYMMETRY) && hat_symmetric(P);
+        R.reverse = !(flags & SK_NO_SYMMETRY);
+        R.part = part;
+        R.parts = parts;
+        s = run_sum(R, res, st);
+        if (s != SK_OK) return s;
+    }
+    for (int i = 0; i < np; ++i) {
+        residues[i] = res[i];
+        st.primes[i] = R.primes[i];
+    }
+    st.nprimes = np;
+    st.passes = 1;
+    st.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    st.ms_per_launch_avg = st.launches ? st.kernel_ms / (double)st.launches : 0.0;
+    g_stats = st;
+    if (stats_out) *stats_out = st;
+    return SK_OK;
+}
+
+sk_status sk_count_combine(int n, int variant, unsigned flags, const uint64_t* residues, uint64_t parts,
+                           sk_u128* out)
+{
+    if (!residues || !out || parts == 0) return SK_EINVAL;
+    Plan P;
+    sk_status s = make_plan(n, variant, P);
+    if (s != SK_OK) return s;
+    const int np = primes_needed(n);
+    const std::vector<uint64_t> primes = default_primes(np, 0);
+    std::vector<uint64_t> res(np, 0);
+    for (uint64_t k = 0; k < parts; ++k)
+        for (int i = 0; i < np; ++i) {
+            const uint64_t r = residues[k * np + i];
+            if (r >= primes[i]) return SK_EINVAL;
+            res[i] = (uint64_t)(((u128)res[i] + r) % primes[i]);
+        }
+    u128 result = 0;
+    if (existence(n, variant) || (flags & SK_NO_SHORTCUT)) {
+        Big c;
+        s = residues_to_count(P, primes, res, c);
+        if (s != SK_OK) return s;
+        result = ((u128)c.w[1] << 64) | c.w[0];
+    }
+    s = halve_reported(n, variant, flags, result);
+    if (s != SK_OK) return s;
+    out->lo = (uint64_t)result;
+    out->hi = (uint64_t)(result >> 64);
     return SK_OK;
 }
 

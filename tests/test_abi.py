@@ -104,3 +104,26 @@ def test_reversal_quadruples_for_skolem_and_langford_only():
         assert sk.describe(n, "langford")["reversal_quads"] >= 2
         if n <= 31:
             assert sk.describe(n, "hooked")["reversal_quads"] == 0
+
+
+def test_count_combine_is_host_only():
+    import oracle as O
+    O.build(force=False)
+    primes = O.primes_below(1 << 46, 4)
+    # no pairing exists: the count is 0 whatever the parts hold
+    assert sk.count_combine(10, "skolem", [[0, 0]] * 4) == 0
+    # a residue out of range is rejected
+    k = sk.describe(12, "skolem")["primes"]
+    with pytest.raises(sk.SkolemError):
+        sk.count_combine(12, "skolem", [[primes[i] for i in range(k)]])
+    # the ordered count C enters as C * 2^(2n - 1 - halved) modulo each prime
+    n = 12
+    d = sk.describe(n, "skolem")
+    C = 455936
+    rows = [[C * pow(2, 2 * n - 1 - d["halved"], primes[i]) % primes[i] for i in range(k)]]
+    assert sk.count_combine(n, "skolem", rows) == C // 2
+    assert sk.count_combine(n, "skolem", rows, ordered=True) == C
+    # split into parts: any additive split of the residues gives the same count
+    split = [[(r * 3) % primes[i] for i, r in enumerate(rows[0])],
+             [(r * -2) % primes[i] for i, r in enumerate(rows[0])]]
+    assert sk.count_combine(n, "skolem", split, ordered=True) == C

@@ -268,3 +268,26 @@ def test_symmetry_reductions_equal_full_sum(variant, n):
         assert r == sk.describe(n, variant)["reversal_quads"] >= 1
     # evaluated: the Lemma 2.4 half, of which reversal keeps 1/2 + 2^-(r+1)
     assert a.stats["terms"] * 2 ** (r + 1) == b.stats["terms"] // 2 * (2 ** r + 1)
+
+
+@pytest.mark.parametrize("variant,n,parts", [("skolem", 16, 8), ("langford", 15, 4), ("hooked", 14, 16),
+                                             ("skolem", 12, 2), ("langford", 19, 32)])
+def test_count_parts_combine_to_the_count(variant, n, parts):
+    """A count split into independent parts (Sec. 2.2) and put together equals
+    the count of one call; another split gives other rows, the same count."""
+    _say("parts", variant, n, parts)
+    rows = [sk.count_part(n, variant, k, parts, ordered=True)[0] for k in range(parts)]
+    want = sk.count(n, variant, ordered=True)
+    assert sk.count_combine(n, variant, rows, ordered=True) == want
+    rows2 = [sk.count_part(n, variant, k, parts // 2, ordered=True)[0] for k in range(parts // 2)]
+    assert sk.count_combine(n, variant, rows2, ordered=True) == want
+    assert sk.count_combine(n, variant, rows) == (want if variant == "hooked" else want // 2)
+
+
+def test_count_parts_reject_bad_splits():
+    with pytest.raises(sk.SkolemError):
+        sk.count_part(16, "skolem", 0, 3)   # not a power of two
+    with pytest.raises(sk.SkolemError):
+        sk.count_part(16, "skolem", 4, 4)   # part out of range
+    with pytest.raises(sk.SkolemError):
+        sk.count_part(16, "skolem", 0, 1 << 40)  # more parts than chunks
