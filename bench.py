@@ -15,6 +15,7 @@ Workloads (all inputs are the problem statements themselves: no data files):
   s20    Skolem n = 20;  l20  Langford n = 20
   s12    Skolem n = 12, two primes (the small correctness case)
   s25    Skolem n = 25 (2^49 sign vectors; the paper used four GPUs)
+  pt     the tempering curve alone (the plain runs' level-moves/s as the value)
   l28slice  Langford n = 28: a seeded 1/4096 subset of its 2^24 prefix chunks
          (2^43 sign vectors) with the three primes a full count needs; the
          projected full-count time is reported
@@ -42,6 +43,7 @@ WORKLOADS = {
     "l20": [("langford", 20)],
     "s12": [("skolem", 12)],
     "l28slice": [("langford", 28)],
+    "pt": [],
     "s25": [("skolem", 25)],
 }
 L28_CHUNK_BITS, L28_SLICE = 24, 4096
@@ -214,7 +216,8 @@ def pt_bench(sk, want, plain_iters, learned_iters, ladders: int, learned_cfg: di
         for it in learned_iters:
             one(n, "learned", it)
     one(32, "plain", plain_iters[-1])
-    one(32, "learned", learned_iters[-1])
+    if learned_iters:
+        one(32, "learned", learned_iters[-1])
     cpu = None
     if cpu_pt:
         import oracle as O
@@ -273,10 +276,30 @@ def main():
         sync = lambda: None  # noqa: E731
 
     instances = WORKLOADS[args.workload]
+    want = expected_values()
+    if args.workload == "pt":
+        learned_cfg = dict(hidden1=256, hidden2=256, first_level=args.pt_learned_first,
+                           plain_per_learned=args.pt_learned_every, snapshots=8, train_steps=400, minibatch=1024,
+                           lr=1e-3, init_seed=1)
+        sync()
+        t0 = time.perf_counter()
+        pt = pt_bench(sk, want, [1 << int(x) for x in args.pt_plain_log2.split(",")],
+                      [1 << int(x) for x in args.pt_learned_log2.split(",") if x], args.pt_ladders, learned_cfg,
+                      cpu_pt=not args.no_cpu_baseline)
+        sync()
+        elapsed = time.perf_counter() - t0
+        plain = [r for r in pt["runs"] if r["proposal"] == "plain"]
+        moves = sum(r["level_moves_per_gpu_s"] * r["gpu_s"] for r in plain)
+        gpu_s = sum(r["gpu_s"] for r in plain)
+        print(json.dumps({"metric": METRIC, "value": moves / gpu_s, "unit": "level-moves/s", "n_gpus": 1,
+                          "steps": 1, "warmup": 0, "ms_per_step": elapsed * 1e3, "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+                          "config": {"workload": "pt", "ladders": args.pt_ladders, "levels": pt["levels"]},
+                          "pt": pt}), flush=True)
+        return
     tuning = {"log2_chunk_terms": args.log2_chunk, "kernel": args.kernel, "waves_per_launch": args.waves}
     if args.workload == "s12":
         tuning["primes"] = 2
-    want = expected_values()
 
     slice_ids = None
     if args.workload == "l28slice":

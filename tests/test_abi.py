@@ -127,3 +127,11 @@ def test_count_combine_is_host_only():
     split = [[(r * 3) % primes[i] for i, r in enumerate(rows[0])],
              [(r * -2) % primes[i] for i, r in enumerate(rows[0])]]
     assert sk.count_combine(n, "skolem", split, ordered=True) == C
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
