@@ -1,6 +1,7 @@
 """Writes tests/golden/l28_slice_chunks.json: partial sums of 16 chunks of the
 Langford n = 28 sign-vector sum (Lemma 2.1), each over 2^31 sign vectors,
-recomputed on the CPU by the oracle's Gray-code walk modulo one prime.
+recomputed on the CPU by the oracle's Gray-code walk modulo the three largest
+primes below 2^46 (the primes a full count of L(28) uses).
 
 The 16 chunks are drawn (SplitMix64, seed 1508) from the 4096-chunk slice
 drawn with seed 1507 out of the 2^24 chunks; the chunk definition (which sign
@@ -39,24 +40,34 @@ def main():
     O.build(force=False)
     slice_ids = inputs.distinct_ids(inputs.SLICE_SEED, C, 4096)
     pick = inputs.subset(inputs.SLICE_SEED + 1, slice_ids, 16)
-    p = O.primes_below(1 << 46, 1)[0]
+    # the three largest primes below 2^46: the primes a full count of L(28) uses
+    primes = O.primes_below(1 << 46, 3)
     out = {"n": N, "variant": VARIANT, "log2_chunks": C, "slice_seed": inputs.SLICE_SEED,
-           "pick_seed": inputs.SLICE_SEED + 1, "prime": p, "chunks": []}
+           "pick_seed": inputs.SLICE_SEED + 1, "prime": primes[0], "primes": primes, "chunks": []}
+    old = {}
     if os.path.exists(OUT):
         with open(OUT) as f:
-            old = json.load(f)
-        if old.get("prime") == p:
-            out["chunks"] = old.get("chunks", [])
-    done = {c["id"] for c in out["chunks"]}
+            prev = json.load(f)
+        for c in prev.get("chunks", []):
+            res = c.get("residues", {})
+            if "residue" in c and prev.get("prime") == primes[0]:
+                res = dict(res, **{str(primes[0]): c["residue"]})
+            old[c["id"]] = (res, c.get("seconds", 0.0))
     for cid in pick:
-        if cid in done:
-            continue
-        t0 = time.time()
-        r = O.chunk_partial(N, VARIANT, chunk_fixed(N, VARIANT, C, cid), p, "gray", threads=threads)
-        out["chunks"].append({"id": cid, "residue": r, "seconds": round(time.time() - t0, 1)})
-        print(cid, r, f"{time.time() - t0:.1f}s", flush=True)
+        res, secs = old.get(cid, ({}, 0.0))
+        for p in primes:
+            if str(p) in res:
+                continue
+            t0 = time.time()
+            res[str(p)] = O.chunk_partial(N, VARIANT, chunk_fixed(N, VARIANT, C, cid), p, "gray", threads=threads)
+            secs += time.time() - t0
+            print(cid, p, res[str(p)], f"{time.time() - t0:.1f}s", flush=True)
+        out["chunks"].append({"id": cid, "residue": res[str(primes[0])], "residues": res,
+                              "seconds": round(secs, 1)})
         with open(OUT, "w") as f:
             json.dump(out, f, indent=1)
+    with open(OUT, "w") as f:
+        json.dump(out, f, indent=1)
 
 
 if __name__ == "__main__":

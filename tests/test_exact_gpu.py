@@ -243,9 +243,12 @@ def test_l28_slice_chunks_match_cpu_recomputation():
     assert len(g["chunks"]) == 16
     ids = [c["id"] for c in g["chunks"]]
     assert set(ids) <= set(inputs.distinct_ids(g["slice_seed"], g["log2_chunks"], 4096))
-    _say("l28 slice: 16 chunks of 2^31 terms")
-    rows = sk.partial_chunks(g["n"], g["variant"], g["log2_chunks"], ids, [g["prime"]])
-    assert [r[0] for r in rows] == [c["residue"] for c in g["chunks"]]
+    primes = g.get("primes", [g["prime"]])
+    _say("l28 slice: 16 chunks of 2^31 terms, primes", len(primes))
+    rows = sk.partial_chunks(g["n"], g["variant"], g["log2_chunks"], ids, primes)
+    for c, row in zip(g["chunks"], rows):
+        want = [int(c.get("residues", {}).get(str(p), c["residue"] if p == g["prime"] else -1)) for p in primes]
+        assert row == want, c["id"]
 
 
 @pytest.mark.parametrize("variant,n", [("skolem", 13), ("langford", 12), ("hooked", 11), ("skolem", 16),
