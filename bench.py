@@ -62,8 +62,8 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # (kernel, workload, log2 sign vectors per work item, waves per launch):
     #     (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact_batch_kernel", "batch", 24, 4096): ("91f52758abca7754", 3208.4375, 10651.4375),
-    ("exact_v2_kernel", "s20", 25, 0): ("6ea75459c3900ab8", 1574.8125, 6272.0),
+    ("exact_batch_kernel", "batch", 24, 4096): ("a6f8595123d507e5", 3190.4375, 10652.0625),
+    ("exact_v2_kernel", "s20", 25, 0): ("7a89797e493ac614", 1568.375, 6272.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 

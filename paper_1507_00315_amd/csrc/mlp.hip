@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sk_mlp.h"
 #include "sk_philox.h"
 
@@ -77,13 +79,18 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs a)
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const long m0 = (long)blockIdx.y * kTile, n0 = (long)blockIdx.x * kTile;
+    // split-K: block z of gridDim.z takes the K range [k_lo, k_hi)
+    const long kc = (a.K + gridDim.z - 1) / gridDim.z;
+    const long kcr = (kc + kTk - 1) / kTk * kTk;
+    const long k_lo = (long)blockIdx.z * kcr;
+    const long k_hi = k_lo + kcr < a.K ? k_lo + kcr : a.K;
     float16v acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
 
     const bool a_mfast = a.sam == 1;  // consecutive m contiguous in memory
     const bool b_nfast = a.sbn == 1;
-    for (long k0 = 0; k0 < a.K; k0 += kTk) {
+    for (long k0 = k_lo; k0 < k_hi; k0 += kTk) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int e = tid + 256 * i;  // 0..1023
@@ -96,7 +103,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs a)
                 mm = e / kTk;
             }
             const long gm = m0 + mm, gk = k0 + kk;
-            As[kk][mm] = (gm < a.M && gk < a.K) ? a.A[gm * a.sam + gk * a.sak] : 0.f;
+            As[kk][mm] = (gm < a.M && gk < k_hi) ? a.A[gm * a.sam + gk * a.sak] : 0.f;
             int nn, kb;
             if (b_nfast) {
                 nn = e % kTile;
@@ -106,7 +113,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs a)
                 nn = e / kTk;
             }
             const long gn = n0 + nn, gkb = k0 + kb;
-            Bs[kb][nn] = (gn < a.N && gkb < a.K) ? a.B[gkb * a.sbk + gn * a.sbn] : 0.f;
+            Bs[kb][nn] = (gn < a.N && gkb < k_hi) ? a.B[gkb * a.sbk + gn * a.sbn] : 0.f;
         }
         __syncthreads();
 #pragma unroll
@@ -122,6 +129,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs a)
         const int row = wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int col = wn * 32 + (lane & 31);
         const long gm = m0 + row, gn = n0 + col;
+        if (gridDim.z > 1) {
+            // partial sums of this K range, combined by splitk_reduce_kernel
+            if (gm < a.M && gn < a.N) a.ws[((long)blockIdx.z * a.M + gm) * a.N + gn] = acc[r];
+            continue;
+        }
         if (gm < a.M && gn < a.N) {
             float v = a.alpha * acc[r];
             if (a.bias) v += a.bias[gn];
@@ -132,6 +144,24 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs a)
             *c = v;
         }
     }
+}
+
+// Sum of the split-K partials in z order (deterministic) and the epilogue of
+// gemm_kernel.
+__global__ void __launch_bounds__(256) splitk_reduce_kernel(const GemmArgs a, int splits)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.M * a.N) return;
+    const long gm = i / a.N, gn = i % a.N;
+    float v = 0.f;
+    for (int z = 0; z < splits; ++z) v += a.ws[(long)z * a.M * a.N + i];
+    v *= a.alpha;
+    if (a.bias) v += a.bias[gn];
+    float* c = a.C + gm * a.scm + gn * a.scn;
+    if (a.accumulate) v += *c;
+    if (a.relu) v = v > 0.f ? v : 0.f;
+    if (a.relu_ref && !(a.relu_ref[gm * a.scm + gn * a.scn] > 0.f)) v = 0.f;
+    *c = v;
 }
 
 // column sums: out[n] = alpha * sum_m Y[m * ld + n].  One block per 64
@@ -468,8 +498,22 @@ hipError_t launch_features(const MlpGeo& g, const uint8_t* states, const float* 
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s)
 {
     if (a.M <= 0 || a.N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(gemm_kernel, dim3((unsigned)((a.N + kTile - 1) / kTile), (unsigned)((a.M + kTile - 1) / kTile)),
+    const long tiles = ((a.N + kTile - 1) / kTile) * ((a.M + kTile - 1) / kTile);
+    // split K when the tiles alone leave most of the 256 CUs idle and K is
+    // long; the partials go to the workspace (splits x M x N floats)
+    int splits = 1;
+    if (a.ws && tiles < 256 && a.K >= 8 * kTk) {
+        const long by_occ = (512 + tiles - 1) / tiles, by_k = a.K / (4 * kTk);
+        splits = (int)std::min<long>({16, by_occ, by_k, a.ws_floats / (a.M * a.N)});
+        if (splits < 2) splits = 1;
+    }
+    hipLaunchKernelGGL(gemm_kernel,
+                       dim3((unsigned)((a.N + kTile - 1) / kTile), (unsigned)((a.M + kTile - 1) / kTile), splits),
                        dim3(256), 0, s, a);
+    if (splits > 1) {
+        const long mn = a.M * a.N;
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, a, splits);
+    }
     return hipGetLastError();
 }
 

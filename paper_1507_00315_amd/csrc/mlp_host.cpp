@@ -60,7 +60,7 @@ void MlpNet::free_batch()
 
 void MlpNet::release()
 {
-    for (float** p : {&P, &Gr, &Mo, &Ve})
+    for (float** p : {&P, &Gr, &Mo, &Ve, &ws})
         if (*p) {
             (void)hipFree(*p);
             *p = nullptr;
@@ -88,6 +88,9 @@ sk_status MlpNet::init(const MlpGeo& geo, int h1_, int h2_, hipStream_t s)
     NET_HIP(hipMalloc(&Ve, count * sizeof(float)));
     NET_HIP(hipMemsetAsync(Mo, 0, count * sizeof(float), s));
     NET_HIP(hipMemsetAsync(Ve, 0, count * sizeof(float), s));
+    // split-K workspace: up to 16 partial copies of the largest weight matrix
+    ws_floats = 16 * (long)std::max({(size_t)h1 * din, (size_t)h2 * h1, (size_t)dout * h2});
+    NET_HIP(hipMalloc(&ws, (size_t)ws_floats * sizeof(float)));
     adam_t = 0;
     return SK_OK;
 }
@@ -134,20 +137,27 @@ static GemmArgs gemm(long M, long N, long K, const float* A, long sam, long sak,
     return a;
 }
 
+hipError_t MlpNet::run_gemm(GemmArgs a, hipStream_t s)
+{
+    a.ws = ws;
+    a.ws_floats = ws_floats;
+    return launch_gemm(a, s);
+}
+
 // Z_out = MLP(X_in) for B rows (activations kept in H1, H2).
 sk_status MlpNet::forward(const float* Xin, float* Zout, int B, hipStream_t s)
 {
     GemmArgs a = gemm(B, h1, din, Xin, din, 1, P + off_W1, 1, din, H1, h1, 1);
     a.bias = P + off_b1;
     a.relu = 1;
-    NET_HIP(launch_gemm(a, s));
+    NET_HIP(run_gemm(a, s));
     a = gemm(B, h2, h1, H1, h1, 1, P + off_W2, 1, h1, H2, h2, 1);
     a.bias = P + off_b2;
     a.relu = 1;
-    NET_HIP(launch_gemm(a, s));
+    NET_HIP(run_gemm(a, s));
     a = gemm(B, dout, h2, H2, h2, 1, P + off_W3, 1, h2, Zout, dout, 1);
     a.bias = P + off_b3;
-    NET_HIP(launch_gemm(a, s));
+    NET_HIP(run_gemm(a, s));
     return SK_OK;
 }
 
@@ -158,22 +168,22 @@ sk_status MlpNet::backward(const uint8_t* states, int B, hipStream_t s)
     NET_HIP(launch_target_grad(g, states, betaf, B, Z, dout, 1.f / (float)B, loss, s));
     // dW3 = dZ^T H2, db3 = colsum dZ
     GemmArgs a = gemm(dout, h2, B, Z, 1, dout, H2, h2, 1, Gr + off_W3, h2, 1);
-    NET_HIP(launch_gemm(a, s));
+    NET_HIP(run_gemm(a, s));
     NET_HIP(launch_colsum(Z, B, dout, dout, 1.f, Gr + off_b3, s));
     // dA2 = (dZ W3) * [H2 > 0]  (into Z2 as scratch, B x h2)
     a = gemm(B, h2, dout, Z, dout, 1, P + off_W3, h2, 1, Z2, h2, 1);
     a.relu_ref = H2;
-    NET_HIP(launch_gemm(a, s));
+    NET_HIP(run_gemm(a, s));
     a = gemm(h2, h1, B, Z2, 1, h2, H1, h1, 1, Gr + off_W2, h1, 1);
-    NET_HIP(launch_gemm(a, s));
+    NET_HIP(run_gemm(a, s));
     NET_HIP(launch_colsum(Z2, B, h2, h2, 1.f, Gr + off_b2, s));
     // dA1 = (dA2 W2) * [H1 > 0]  (Z2 holds at least B x (h2 + h1) floats)
     float* dA1 = Z2 + (size_t)B * h2;
     a = gemm(B, h1, h2, Z2, h2, 1, P + off_W2, h1, 1, dA1, h1, 1);
     a.relu_ref = H1;
-    NET_HIP(launch_gemm(a, s));
+    NET_HIP(run_gemm(a, s));
     a = gemm(h1, din, B, dA1, 1, h1, X, din, 1, Gr + off_W1, din, 1);
-    NET_HIP(launch_gemm(a, s));
+    NET_HIP(run_gemm(a, s));
     NET_HIP(launch_colsum(dA1, B, h1, h1, 1.f, Gr + off_b1, s));
     return SK_OK;
 }

@@ -14,6 +14,8 @@ struct MlpGeo {
 
 // C[m, n] = alpha * sum_k A[m, k] B[k, n] (+ bias[n]) (+ C if accumulate),
 // then max(., 0) if relu, then 0 where relu_ref[m, n] <= 0 (if given).
+// With a workspace, short-and-wide products (few output tiles, long K) are
+// split along K and the partials summed in a fixed order.
 // Element (i, j) of a matrix X sits at X[i * s_i + j * s_j].
 struct GemmArgs {
     long M, N, K;
@@ -28,6 +30,8 @@ struct GemmArgs {
     int relu;
     int accumulate;
     float alpha;
+    float* ws;       // nullptr, or a workspace of ws_floats floats that allows split-K
+    long ws_floats;
 };
 
 hipError_t launch_features(const MlpGeo& g, const uint8_t* states, const float* beta, int B, float* X, int ldx,

@@ -20,6 +20,8 @@ struct MlpNet {
     int din = 0, h1 = 0, h2 = 0, dout = 0;
     size_t off_W1 = 0, off_b1 = 0, off_W2 = 0, off_b2 = 0, off_W3 = 0, off_b3 = 0, count = 0;
     float *P = nullptr, *Gr = nullptr, *Mo = nullptr, *Ve = nullptr;  // params, grads, Adam moments
+    float* ws = nullptr;  // split-K workspace of the GEMMs
+    long ws_floats = 0;
     // per-batch buffers for up to cap states: features X (B x din), hidden
     // activations H1, H2, logits Z (B x dout); X2, Z2 hold the second forward
     // pass of a proposal (at C') and the backward scratch
@@ -43,6 +45,7 @@ struct MlpNet {
     sk_status init(const MlpGeo& geo, int h1, int h2, hipStream_t s);
     sk_status reserve(int B);
     sk_status set_betas(const double* betas, int B, hipStream_t s);
+    hipError_t run_gemm(GemmArgs a, hipStream_t s);
     sk_status forward(const float* Xin, float* Zout, int B, hipStream_t s);
     sk_status backward(const uint8_t* states, int B, hipStream_t s);
     sk_status adam_step(float lr, hipStream_t s);

@@ -100,8 +100,9 @@ def test_prime_count_covers_the_count_bound():
 def test_reversal_quadruples_for_skolem_and_langford_only():
     # Lemma 2.3 needs a position set symmetric under i -> 2n + 1 - i
     for n in range(12, 33):
-        assert sk.describe(n, "skolem")["reversal_quads"] >= 2
-        assert sk.describe(n, "langford")["reversal_quads"] >= 2
+        for v in ("skolem", "langford"):
+            r = sk.describe(n, v)["reversal_quads"]
+            assert r >= 2 and (r == 4 or n < 22), (v, n, r)  # large instances walk n - 9 variables
         if n <= 31:
             assert sk.describe(n, "hooked")["reversal_quads"] == 0
 

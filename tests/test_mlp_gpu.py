@@ -64,6 +64,7 @@ SHAPES = [  # (variant, n, h1, h2, batch): ragged tiles in every GEMM dimension
     ("langford", 7, 64, 72, 37),
     ("hooked", 5, 33, 65, 129),
     ("skolem", 32, 256, 256, 70),   # the full-size network (130 -> 256 -> 256 -> 2048)
+    ("langford", 6, 96, 64, 1024),  # long batch: weight gradients split along K
 ]
 
 
