@@ -13,9 +13,10 @@
  * coefficient of x_1...x_{2n} in prod_k f_k with f_k = sum_i x_i x_{i+d_k},
  * equal to 2^{-2n} times the sum over x in {+1,-1}^{2n} of (prod x) prod_k f_k.
  * The library evaluates the half of the sum with the first sign fixed to +1
- * (Lemma 2.2), visits sign vectors in Gray-code order on the GPU, takes the
- * products modulo several primes below 2^46 and recombines them on the host by
- * the Chinese remainder theorem (Sec. 2.2).
+ * (Lemma 2.2), further reduced by the even-position symmetry (Lemma 2.4) and
+ * the reversal symmetry (Lemma 2.3), visits sign vectors in Gray-code order on
+ * the GPU, takes the products modulo several primes below 2^46 and recombines
+ * them on the host by the Chinese remainder theorem (Sec. 2.2).
  *
  * Conventions for every entry point:
  *   - All pointers are host pointers unless the name says dev_.
@@ -100,8 +101,8 @@ typedef struct {
 typedef struct {
     double kernel_ms;        /* sum of kernel durations (HIP events on the launch stream) */
     double wall_ms;          /* whole call, host clock */
-    uint64_t terms;          /* sign vectors evaluated (x_1 fixed; half of them when
-                                symmetry_halved) */
+    uint64_t terms;          /* sign vectors evaluated (x_1 fixed; fewer when the
+                                symmetries apply: symmetry_halved, reversal_quads) */
     uint64_t launches;       /* kernel launches */
     uint64_t chunks;         /* wavefront work units */
     int nprimes;             /* primes used per pass */
@@ -123,7 +124,7 @@ sk_status sk_set_device(int device);
 /*
  * sk_count -- exact number of pairings for (n, variant), Sec. 2.
  *   n       : 1..32 (Skolem, Langford), 1..31 (hooked)
- *   flags   : SK_ORDERED | SK_NO_SHORTCUT | SK_VERIFY
+ *   flags   : SK_ORDERED | SK_NO_SHORTCUT | SK_VERIFY | SK_NO_SYMMETRY
  *   out     : receives the count
  * Errors: SK_EINVAL, SK_EDEVICE, SK_ECHECK (CRT result above the a priori bound
  * n!, or the SK_VERIFY passes disagree), SK_ENOLIB.
@@ -151,6 +152,8 @@ sk_status sk_count_ex(int n, int variant, unsigned flags, const sk_tuning *tune,
  *              (SK_EINVAL otherwise); part < parts
  *   residues : sk_count_part: sk_describe(...).primes outputs in [0, p);
  *              sk_count_combine: parts x primes, row k from part k
+ * The shares follow the library's own chunking of the instance, so all parts
+ * of one count must come from the same build (and the same tune).
  * SK_VERIFY is not accepted by sk_count_part.  Errors: as sk_count.
  */
 sk_status sk_count_part(int n, int variant, unsigned flags, uint64_t part, uint64_t parts,
