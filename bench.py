@@ -62,8 +62,8 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # (kernel, workload, log2 sign vectors per work item, waves per launch):
     #     (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact_batch_kernel", "batch", 24, 4096): ("a6f8595123d507e5", 3190.4375, 10652.0625),
-    ("exact_v2_kernel", "s20", 25, 0): ("7a89797e493ac614", 1568.375, 6272.0),
+    ("exact_batch_kernel", "batch", 24, 4096): ("6616765c13036495", 3372.625, 6554.75),
+    ("exact_v2_kernel", "s20", 25, 0): ("3ce3064d1f2f1481", 161.0, 128.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
@@ -412,6 +412,7 @@ def main():
                    "terms_per_step": terms_per_step,
                    "primes_per_instance": {f"{v}:{n}": sk.describe(n, v)["primes"] for v, n in instances},
                    "log2_chunk_terms": stats_of(results[0])[0]["log2_chunk_terms"],
+                   "waves_per_launch": launch_waves,
                    "lemma_2_4_halving": bool(stats_of(results[0])[0].get("symmetry_halved")),
                    "sign_vectors_covered_per_step": covered,
                    "sign_vectors_covered_per_s": covered * args.steps / elapsed,

@@ -60,12 +60,14 @@ __host__ __device__ constexpr PlanCE make_plan_ce(int n, int variant, int walk_c
     for (int k = 1; k <= n; ++k) P.d[k - 1] = variant == 1 ? k + 1 : k;
     P.n_lane = kLaneBits < P.m - 1 ? kLaneBits : P.m - 1;
     {
-        // For large Skolem and Langford instances the walk stops at n - 9
-        // variables, so that the job variables hold the mirror pairs of eight
-        // middle positions: four reversal quadruples (Lemma 2.3), which skip
-        // 15/32 of the jobs instead of 7/16.  A job still walks at least 2^13
-        // sign vectors per lane there, so the per-job set-up stays negligible.
-        const int cap = (variant != 2 && n >= 22 && n - 9 < walk_cap) ? n - 9 : walk_cap;
+        // For Skolem and Langford instances from n = 15 on the walk stops at
+        // n - 9 variables (one or two short of the longest walk), so that the
+        // job variables hold the mirror pairs of eight middle positions: four
+        // reversal quadruples (Lemma 2.3), which skip 15/32 of the jobs
+        // instead of 7/16.  A job walks 2^(n-9) sign vectors per lane, at
+        // least 2^11 for the instances that dominate a count (n >= 20), so
+        // the per-job set-up stays below a percent there.
+        const int cap = (variant != 2 && n >= 15 && n - 9 < walk_cap) ? n - 9 : walk_cap;
         const int dmax = P.d[n - 1];
         int w = 0;
         while (w + 1 <= P.m - 1 - P.n_lane && w + 1 <= cap && P.pos[w + 1] + dmax < P.pos[P.m - P.n_lane])

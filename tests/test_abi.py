@@ -102,7 +102,7 @@ def test_reversal_quadruples_for_skolem_and_langford_only():
     for n in range(12, 33):
         for v in ("skolem", "langford"):
             r = sk.describe(n, v)["reversal_quads"]
-            assert r >= 2 and (r == 4 or n < 22), (v, n, r)  # large instances walk n - 9 variables
+            assert r >= 2 and (r == 4 or n < 15), (v, n, r)  # from n = 15 on the walk is n - 9 variables
         if n <= 31:
             assert sk.describe(n, "hooked")["reversal_quads"] == 0
 
