@@ -31,13 +31,13 @@
 namespace sk {
 
 // Placement index -> left position of pair k (1-based), for the variant's
-// position set.
-// (written as selects, so that the move stays one basic block)
+// position set.  Hooked: positions 1..2n-1 and 2n+1; the first 2n-1-d
+// placements end at or below 2n-1, the last one ends at 2n+1.  Written with
+// bitwise operators so that it compiles to selects, not branches.
 __device__ __forceinline__ int placement(const PtArgs& a, int d, int idx)
 {
-    // hooked: 1..2n-1 and 2n+1; the first 2n-1-d placements end at or below
-    // 2n-1, the last one ends at 2n+1
-    return (a.variant == 2 && idx >= 2 * a.n - 1 - d) ? 2 * a.n + 1 - d : 1 + idx;
+    const bool past_hole = (a.variant == 2) & (idx >= 2 * a.n - 1 - d);
+    return past_hole ? 2 * a.n + 1 - d : 1 + idx;
 }
 
 // The value held by lane + 1 / lane - 1 (wavefront shifts by one lane, DPP;
@@ -56,7 +56,7 @@ __device__ __forceinline__ int pair_diff(const PtArgs& a, int k) { return k + 1 
 
 __device__ __forceinline__ int placements_of(const PtArgs& a, int d)
 {
-    return 2 * a.n - d - (a.variant == 2 && d == 1);
+    return 2 * a.n - d - ((a.variant == 2) & (d == 1));
 }
 
 __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
@@ -79,18 +79,25 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
         swap_thr[i] = a.swap_thr[i];
     }
 
-    int slot = lane;
+    // Every lane, also the ones above the top level, owns a configuration slot
+    // and runs the moves on it, so that the iteration needs no lane-dependent
+    // branch.  Those lanes never take part in an exchange (so their slots stay
+    // their own), their histogram increments are 0 and go to row 0, and their
+    // results are never written out.
+    int sb = lane * slot_bytes;  // LDS byte offset of the lane's current slot
     int E = 0;
-    uint32_t T1 = 0, T2 = 0;
     uint32_t mv_acc = 0, sw_acc = 0;
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    if (live) {
-        T1 = a.move_thr[lane * 2 + 0];
-        T2 = a.move_thr[lane * 2 + 1];
-        uint8_t* s = slots + (size_t)slot * slot_bytes;
+    const uint32_t T1 = live ? a.move_thr[lane * 2 + 0] : 0u;
+    const uint32_t T2 = live ? a.move_thr[lane * 2 + 1] : 0u;
+    const uint32_t hinc = live ? 1u : 0u;
+    uint32_t* const hrow = hist + (live ? lane * H : 0);
+    const uint32_t* const trow = swap_thr + (live ? lane * H : 0);
+    {
+        uint8_t* s = slots + sb;
         uint8_t* occ = s + n;
         for (int p = 0; p <= top; ++p) occ[p] = 0;
-        if (a.state_in) {
+        if (live && a.state_in) {
             const uint8_t* src = a.state_in + ((size_t)ladder * M + lane) * n;
             for (int k = 0; k < n; ++k) s[k] = src[k];
         } else {
@@ -115,72 +122,86 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     }
     __syncthreads();
 
-    // The words of iteration it + 1 are drawn during iteration it (they depend
-    // on nothing the iteration computes), so their arithmetic fills the wait
-    // for the iteration's first LDS read.
-    uint32_t rn[4];
-    philox4x32_10((uint32_t)a.it_begin, (uint32_t)(a.it_begin >> 32), ladder, (uint32_t)lane, k0, k1, rn);
+    // Software pipeline.  The Philox words are drawn two iterations ahead:
+    // iteration it holds the words of it (r) and it + 1 (rn) and draws those
+    // of it + 2, in two pieces that fill the waits for the iteration's two
+    // dependent LDS round trips (the four occupancies; the exchange threshold).
+    // The byte s[k] that the next move starts from is read in the second round
+    // trip, for each of the three slots the lane can hold after the exchange
+    // (its own, the one above, the one below), and picked once the exchange is
+    // decided.  The scheduling barriers keep each piece of Philox arithmetic
+    // between a read and the first use of its value.
+    uint32_t r[4], rn[4];
+    philox4x32_10((uint32_t)a.it_begin, (uint32_t)(a.it_begin >> 32), ladder, (uint32_t)lane, k0, k1, r);
+    philox4x32_10((uint32_t)(a.it_begin + 1), (uint32_t)((a.it_begin + 1) >> 32), ladder, (uint32_t)lane, k0, k1,
+                  rn);
+    int k = (int)__umulhi(r[0], (uint32_t)n);
+    int a_old = slots[sb + k];
     for (uint64_t it = a.it_begin; it < a.it_end; ++it) {
-        // 1. record (LDS atomic add: no read-back, each lane owns its row)
-        if (live) atomicAdd(&hist[lane * H + E], 1u);
-        // 2. move
-        const uint32_t r[4] = {rn[0], rn[1], rn[2], rn[3]};
-        if (live) {
-            uint8_t* s = slots + (size_t)slot * slot_bytes;
-            uint8_t* occ = s + n;
-            const int k = (int)__umulhi(r[0], (uint32_t)n);
-            const int d = pair_diff(a, k);
-            const int idx = (int)__umulhi(r[1], (uint32_t)placements_of(a, d));
-            const int a_new = placement(a, d, idx);
-            const int a_old = s[k];
-            // next iteration's words while the read of s[k] is in flight (the
-            // lanes above the top level never use theirs); the scheduling
-            // barrier keeps the read issued ahead of them
-            __builtin_amdgcn_sched_barrier(0);
-            philox4x32_10((uint32_t)(it + 1), (uint32_t)((it + 1) >> 32), ladder, (uint32_t)lane, k0, k1, rn);
-            const int b_old = a_old + d, b_new = a_new + d;
-            // the four occupancies in one round trip; the positions may
-            // coincide (a_new == a_old, a_new == b_old, b_new == a_old), which
-            // the energy change and the final counts account for in registers
-            const int o1 = occ[a_old], o2 = occ[b_old], o3 = occ[a_new], o4 = occ[b_new];
-            const int c3 = o3 - (a_new == a_old) - (a_new == b_old);  // after removing pair k
-            const int c4 = o4 - (b_new == a_old) - (b_new == b_old);
-            const int de = (o1 == 1) + (o2 == 1) - (c3 == 0) - (c4 == 0);
-            const bool acc = de <= 0 || r[2] < (de == 1 ? T1 : T2);
-            // final counts of the (possibly repeated) four positions, written
-            // whether or not the move is accepted (a rejected move writes back
-            // what it read); a repeated position receives the same value from
-            // every write
-            const int ac = acc ? 1 : 0;
-            occ[a_old] = (uint8_t)(o1 + ac * ((a_old == a_new) + (a_old == b_new) - 1));
-            occ[b_old] = (uint8_t)(o2 + ac * ((b_old == a_new) + (b_old == b_new) - 1));
-            occ[a_new] = (uint8_t)(acc ? c3 + 1 : o3);
-            occ[b_new] = (uint8_t)(acc ? c4 + 1 : o4);
-            s[k] = (uint8_t)(acc ? a_new : a_old);
-            E += ac * de;
-            mv_acc += ac;
-        }
-        // 3. exchange (j, j+1) with j of the iteration's parity
+        // 1. move (pair k, whose current left position a_old was read ahead)
+        uint8_t* s = slots + sb;
+        uint8_t* occ = s + n;
+        const int d = pair_diff(a, k);
+        const int idx = (int)__umulhi(r[1], (uint32_t)placements_of(a, d));
+        const int a_new = placement(a, d, idx);
+        const int b_old = a_old + d, b_new = a_new + d;
+        // the four occupancies in one round trip; the positions may coincide
+        // (a_new == a_old, a_new == b_old, b_new == a_old), which the energy
+        // change and the final counts account for in registers
+        const int o1 = occ[a_old], o2 = occ[b_old], o3 = occ[a_new], o4 = occ[b_new];
+        // 2. record the energy before the move (LDS atomic add, no read-back;
+        // each level owns its row); issued behind the reads it does not feed
+        atomicAdd(&hrow[E], hinc);
+        uint32_t c[4] = {(uint32_t)(it + 2), (uint32_t)((it + 2) >> 32), ladder, (uint32_t)lane};
+        __builtin_amdgcn_sched_barrier(0);
+        philox4x32_rounds<0, 5>(c, k0, k1);
+        __builtin_amdgcn_sched_barrier(0);
+        const int c3 = o3 - (a_new == a_old) - (a_new == b_old);  // after removing pair k
+        const int c4 = o4 - (b_new == a_old) - (b_new == b_old);
+        const int de = (o1 == 1) + (o2 == 1) - (c3 == 0) - (c4 == 0);
+        const bool acc = de <= 0 || r[2] < (de == 1 ? T1 : T2);
+        // final counts of the (possibly repeated) four positions, written
+        // whether or not the move is accepted (a rejected move writes back what
+        // it read); a repeated position receives the same value from every write
+        const int ac = acc ? 1 : 0;
+        occ[a_old] = (uint8_t)(o1 + ac * ((a_old == a_new) + (a_old == b_new) - 1));
+        occ[b_old] = (uint8_t)(o2 + ac * ((b_old == a_new) + (b_old == b_new) - 1));
+        occ[a_new] = (uint8_t)(acc ? c3 + 1 : o3);
+        occ[b_new] = (uint8_t)(acc ? c4 + 1 : o4);
+        s[k] = (uint8_t)(acc ? a_new : a_old);
+        E += ac * de;
+        mv_acc += ac;
+        // 3. exchange (j, j+1) with j of the iteration's parity; the threshold
+        // is read for every lane (index clamped at 0, where it is not needed),
+        // and the next move's s[k] for the three candidate slots (after the
+        // writes above, so they see this move)
         const int parity = (int)(it & 1);
         const int E_up = from_lane_above(E);
-        const int slot_up = from_lane_above(slot);
-        const bool lower = live && lane + 1 < M && (lane & 1) == parity;
-        bool sw = false;
-        if (lower) {
-            const int de = E - E_up;
-            sw = de <= 0 || r[3] < swap_thr[lane * H + de];
-        }
+        const int sb_up = from_lane_above(sb);
+        const int sb_dn = from_lane_below(sb);
+        const int dx = E - E_up;
+        const uint32_t thr = trow[dx > 0 ? dx : 0];
+        const int k_next = (int)__umulhi(rn[0], (uint32_t)n);
+        const int v_own = slots[sb + k_next];
+        const int v_up = slots[sb_up + k_next];
+        const int v_dn = slots[sb_dn + k_next];
+        __builtin_amdgcn_sched_barrier(0);
+        philox4x32_rounds<5, 10>(c, k0, k1);
+        __builtin_amdgcn_sched_barrier(0);
+        const bool lower = (lane + 1 < M) & ((lane & 1) == parity);
+        const bool sw = lower & ((dx <= 0) | (r[3] < thr));
         const int sw_from_below = from_lane_below((int)sw);
         const int E_dn = from_lane_below(E);
-        const int slot_dn = from_lane_below(slot);
-        const bool upper = live && lane >= 1 && ((lane - 1) & 1) == parity && sw_from_below;
-        if (sw) {
-            E = E_up;
-            slot = slot_up;
-            ++sw_acc;
-        } else if (upper) {
-            E = E_dn;
-            slot = slot_dn;
+        const bool upper = (lane >= 1) & (lane < M) & (((lane - 1) & 1) == parity) & (sw_from_below != 0);
+        E = sw ? E_up : (upper ? E_dn : E);
+        sb = sw ? sb_up : (upper ? sb_dn : sb);
+        a_old = sw ? v_up : (upper ? v_dn : v_own);
+        sw_acc += sw ? 1u : 0u;
+        k = k_next;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            r[i] = rn[i];
+            rn[i] = c[i];
         }
     }
     __syncthreads();
@@ -191,7 +212,7 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
         a.move_acc[(size_t)ladder * M + lane] += mv_acc;
         a.swap_acc[(size_t)ladder * M + lane] += sw_acc;
         a.energy_out[(size_t)ladder * M + lane] = E;
-        const uint8_t* s = slots + (size_t)slot * slot_bytes;
+        const uint8_t* s = slots + sb;
         uint8_t* dst = a.state_out + ((size_t)ladder * M + lane) * n;
         for (int k = 0; k < n; ++k) dst[k] = s[k];
     }

@@ -9,30 +9,35 @@
 
 namespace sk {
 
+// Rounds R0 .. R1-1 of Philox4x32 on the counter block c (in place); round r
+// uses the key (k0 + r W0, k1 + r W1).  Running the rounds in pieces lets a
+// kernel spread one block's arithmetic over several memory waits.
+template <int R0, int R1>
+__device__ __forceinline__ void philox4x32_rounds(uint32_t (&c)[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = R0; r < R1; ++r) {
+        const uint32_t kr0 = k0 + (uint32_t)r * 0x9E3779B9u;
+        const uint32_t kr1 = k1 + (uint32_t)r * 0xBB67AE85u;
+        const uint32_t lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        c[0] = hi1 ^ c[1] ^ kr0;
+        c[1] = lo1;
+        c[2] = hi0 ^ c[3] ^ kr1;
+        c[3] = lo0;
+    }
+}
+
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                               uint32_t k1, uint32_t (&out)[4])
 {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r > 0) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-    }
     out[0] = c0;
     out[1] = c1;
     out[2] = c2;
     out[3] = c3;
+    philox4x32_rounds<0, 10>(out, k0, k1);
 }
 
 }  // namespace sk
