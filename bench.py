@@ -214,6 +214,7 @@ def pt_bench(sk, want, plain_iters, learned_iters, ladders: int, learned_cfg: di
             + (f"  rel err {rec['rel_error']:.2e}" if exact else "") + f"  gpu {rec['gpu_s']:.3f} s")
         runs.append(rec)
 
+    sk.approx(20, "skolem", betas, ladders=ladders, iterations=1 << 10, seed=seed)  # warm-up, not recorded
     for n in (20, 24):
         for it in plain_iters:
             one(n, "plain", it)
