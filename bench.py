@@ -45,6 +45,10 @@ WORKLOADS = {
     "l28slice": [("langford", 28)],
     "pt": [],
     "s25": [("skolem", 25)],
+    # every nonzero S(n) and L(n) up to n = 24 (existence: S needs n = 0, 1 mod 4,
+    # L needs n = 0, 3 mod 4), largest first
+    "all24": sorted([("skolem", n) for n in range(1, 25) if n % 4 in (0, 1)] +
+                    [("langford", n) for n in range(1, 25) if n % 4 in (0, 3)], key=lambda x: -x[1]),
 }
 L28_CHUNK_BITS, L28_SLICE = 24, 4096
 
