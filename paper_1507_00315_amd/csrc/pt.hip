@@ -31,13 +31,15 @@
 namespace sk {
 
 // Placement index -> left position of pair k (1-based), for the variant's
-// position set.  Hooked: positions 1..2n-1 and 2n+1; the first 2n-1-d
-// placements end at or below 2n-1, the last one ends at 2n+1.  Written with
-// bitwise operators so that it compiles to selects, not branches.
-__device__ __forceinline__ int placement(const PtArgs& a, int d, int idx)
+// position set (V: 0 Skolem, 1 Langford, 2 hooked; a compile-time constant, so
+// the hooked case costs the other two nothing).  Hooked: positions 1..2n-1 and
+// 2n+1; the first 2n-1-d placements end at or below 2n-1, the last one ends at
+// 2n+1.
+template <int V>
+__device__ __forceinline__ int placement(int n, int d, int idx)
 {
-    const bool past_hole = (a.variant == 2) & (idx >= 2 * a.n - 1 - d);
-    return past_hole ? 2 * a.n + 1 - d : 1 + idx;
+    if constexpr (V == 2) return idx >= 2 * n - 1 - d ? 2 * n + 1 - d : 1 + idx;
+    return 1 + idx;
 }
 
 // The value held by lane + 1 / lane - 1 (wavefront shifts by one lane, DPP;
@@ -52,13 +54,19 @@ __device__ __forceinline__ int from_lane_below(int x)
     return __builtin_amdgcn_update_dpp(x, x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
 }
 
-__device__ __forceinline__ int pair_diff(const PtArgs& a, int k) { return k + 1 + (a.variant == 1); }
-
-__device__ __forceinline__ int placements_of(const PtArgs& a, int d)
+template <int V>
+__device__ __forceinline__ int pair_diff(int k)
 {
-    return 2 * a.n - d - ((a.variant == 2) & (d == 1));
+    return k + 1 + (V == 1);
 }
 
+template <int V>
+__device__ __forceinline__ int placements_of(int n, int d)
+{
+    return 2 * n - d - (V == 2 && d == 1);
+}
+
+template <int V>
 __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
 {
     extern __shared__ uint8_t lds[];
@@ -106,14 +114,14 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
                 philox4x32_10(0xFFFFFFF0u + (uint32_t)blk, 0xFFFFFFFFu, ladder, (uint32_t)lane, k0, k1, r);
                 for (int t = 0; t < 4 && blk * 4 + t < n; ++t) {
                     const int k = blk * 4 + t;
-                    const int d = pair_diff(a, k);
-                    const int idx = (int)__umulhi(r[t], (uint32_t)placements_of(a, d));
-                    s[k] = (uint8_t)placement(a, d, idx);
+                    const int d = pair_diff<V>(k);
+                    const int idx = (int)__umulhi(r[t], (uint32_t)placements_of<V>(n, d));
+                    s[k] = (uint8_t)placement<V>(n, d, idx);
                 }
             }
         }
         for (int k = 0; k < n; ++k) {
-            const int d = pair_diff(a, k);
+            const int d = pair_diff<V>(k);
             occ[s[k]]++;
             occ[s[k] + d]++;
         }
@@ -141,9 +149,9 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
         // 1. move (pair k, whose current left position a_old was read ahead)
         uint8_t* s = slots + sb;
         uint8_t* occ = s + n;
-        const int d = pair_diff(a, k);
-        const int idx = (int)__umulhi(r[1], (uint32_t)placements_of(a, d));
-        const int a_new = placement(a, d, idx);
+        const int d = pair_diff<V>(k);
+        const int idx = (int)__umulhi(r[1], (uint32_t)placements_of<V>(n, d));
+        const int a_new = placement<V>(n, d, idx);
         const int b_old = a_old + d, b_new = a_new + d;
         // the four occupancies in one round trip; the positions may coincide
         // (a_new == a_old, a_new == b_old, b_new == a_old), which the energy
@@ -220,7 +228,12 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
 
 hipError_t launch_pt_ladders(unsigned ladders, size_t lds_bytes, hipStream_t stream, const PtArgs& a)
 {
-    hipLaunchKernelGGL(pt_ladder_kernel, dim3(ladders), dim3(64), lds_bytes, stream, a);
+    switch (a.variant) {
+        case 0: hipLaunchKernelGGL(pt_ladder_kernel<0>, dim3(ladders), dim3(64), lds_bytes, stream, a); break;
+        case 1: hipLaunchKernelGGL(pt_ladder_kernel<1>, dim3(ladders), dim3(64), lds_bytes, stream, a); break;
+        case 2: hipLaunchKernelGGL(pt_ladder_kernel<2>, dim3(ladders), dim3(64), lds_bytes, stream, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
