@@ -23,9 +23,14 @@ __device__ __forceinline__ void philox4x32_rounds(uint32_t (&c)[4], uint32_t k0,
         const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
         const uint32_t lo1 = 0xCD9E8D57u * c[2];
         const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
-        c[0] = hi1 ^ c[1] ^ kr0;
+        // three-input XOR in one instruction (v_bitop3_b32, truth table 0x96);
+        // rounds 0 and 1 keep plain XORs, whose operands are often wave-uniform
+        // (counter words shared by the wave), so they stay on the scalar unit
+        const uint32_t n0 = r >= 2 ? __builtin_amdgcn_bitop3_b32(hi1, c[1], kr0, 0x96) : hi1 ^ c[1] ^ kr0;
+        const uint32_t n2 = r >= 2 ? __builtin_amdgcn_bitop3_b32(hi0, c[3], kr1, 0x96) : hi0 ^ c[3] ^ kr1;
+        c[0] = n0;
         c[1] = lo1;
-        c[2] = hi0 ^ c[3] ^ kr1;
+        c[2] = n2;
         c[3] = lo0;
     }
 }
