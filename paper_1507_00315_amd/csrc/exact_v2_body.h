@@ -445,6 +445,17 @@ __device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const Rev
     });
 }
 
+// A wave-uniform fp64 value copied into a vector register pair, so that it
+// takes no scalar registers: the scalar unit's pair-sum state (B and the N_q)
+// of the large instances needs all of them, and the primes and their inverses
+// are read only as fp64 operands.
+__device__ __forceinline__ double in_vgpr(double x)
+{
+    double r;
+    asm("v_mov_b64 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
 {
     return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
@@ -460,8 +471,8 @@ __global__ void __launch_bounds__(256) exact_v2_kernel(const ExactArgsV2 a, doub
     double pr[P], pinv[P], res[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-        pr[i] = a.prime[i];
-        pinv[i] = a.pinv[i];
+        pr[i] = in_vgpr(a.prime[i]);
+        pinv[i] = in_vgpr(a.pinv[i]);
     }
     exact_v2_chunk<V, N, P, INNER>(chunk, a.job_bits_per_chunk, a.rev, pr, pinv, res);
     if ((threadIdx.x & 63) == 0) {
