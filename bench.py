@@ -66,8 +66,8 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # (kernel, workload, log2 sign vectors per work item, waves per launch):
     #     (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact_batch_kernel", "batch", 24, 4096): ("6616765c13036495", 3372.625, 6554.75),
-    ("exact_v2_kernel", "s20", 25, 0): ("3ce3064d1f2f1481", 161.0, 128.0),
+    ("exact_batch_kernel", "batch", 24, 4096): ("a519d991164ffec3", 3366.0, 6554.65625),
+    ("exact_v2_kernel", "s20", 25, 0): ("5996699165dbafe6", 158.5, 128.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
