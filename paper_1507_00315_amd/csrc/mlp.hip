@@ -71,6 +71,20 @@ __global__ void __launch_bounds__(256) mlp_features_kernel(MlpGeo g, const uint8
 
 constexpr int kTile = 64, kTk = 16;
 
+// Element i (0..2047) of a 64 x kTk operand tile: its (row within the tile, k)
+// pair.  Consecutive threads take consecutive addresses in memory: along the
+// row index when that is the contiguous dimension, else along k.
+__device__ __forceinline__ void tile_coords(int e, bool row_fast, int& rr, int& kk)
+{
+    if (row_fast) {
+        rr = e % kTile;
+        kk = e / kTile;
+    } else {
+        kk = e % kTk;
+        rr = e / kTk;
+    }
+}
+
 __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs a)
 {
     __shared__ float As[kTk][kTile + 4];
@@ -90,32 +104,39 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs a)
 
     const bool a_mfast = a.sam == 1;  // consecutive m contiguous in memory
     const bool b_nfast = a.sbn == 1;
-    for (long k0 = k_lo; k0 < k_hi; k0 += kTk) {
+    constexpr int kPer = kTile * kTk / 256;  // elements of each operand per thread
+    // The next tile's elements are loaded into registers while the MFMAs work
+    // on the current one (held in LDS), so the global loads' latency hides
+    // behind the arithmetic.
+    // (32-bit offsets: launch_gemm checks that every operand index fits)
+    float ra[kPer], rb[kPer];
+    const int M = (int)a.M, N = (int)a.N, kh = (int)k_hi;
+    const int sam = (int)a.sam, sak = (int)a.sak, sbk = (int)a.sbk, sbn = (int)a.sbn;
+    auto load = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = tid + 256 * i;  // 0..1023
-            int mm, kk;
-            if (a_mfast) {
-                mm = e % kTile;
-                kk = e / kTile;
-            } else {
-                kk = e % kTk;
-                mm = e / kTk;
-            }
-            const long gm = m0 + mm, gk = k0 + kk;
-            As[kk][mm] = (gm < a.M && gk < k_hi) ? a.A[gm * a.sam + gk * a.sak] : 0.f;
-            int nn, kb;
-            if (b_nfast) {
-                nn = e % kTile;
-                kb = e / kTile;
-            } else {
-                kb = e % kTk;
-                nn = e / kTk;
-            }
-            const long gn = n0 + nn, gkb = k0 + kb;
-            Bs[kb][nn] = (gn < a.N && gkb < k_hi) ? a.B[gkb * a.sbk + gn * a.sbn] : 0.f;
+        for (int i = 0; i < kPer; ++i) {
+            const int e = tid + 256 * i;
+            int mm, kk, nn, kb;
+            tile_coords(e, a_mfast, mm, kk);
+            tile_coords(e, b_nfast, nn, kb);
+            const int gm = (int)m0 + mm, gk = k0 + kk, gn = (int)n0 + nn, gkb = k0 + kb;
+            ra[i] = (gm < M && gk < kh) ? a.A[gm * sam + gk * sak] : 0.f;
+            rb[i] = (gn < N && gkb < kh) ? a.B[gkb * sbk + gn * sbn] : 0.f;
+        }
+    };
+    if (k_lo < k_hi) load((int)k_lo);
+    for (int k0 = (int)k_lo; k0 < kh; k0 += kTk) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = tid + 256 * i;
+            int mm, kk, nn, kb;
+            tile_coords(e, a_mfast, mm, kk);
+            tile_coords(e, b_nfast, nn, kb);
+            As[kk][mm] = ra[i];
+            Bs[kb][nn] = rb[i];
         }
         __syncthreads();
+        if (k0 + kTk < kh) load(k0 + kTk);
 #pragma unroll
         for (int kk = 0; kk < kTk; kk += 2) {
             const float av = As[kk + (lane >> 5)][wm * 32 + (lane & 31)];
@@ -165,8 +186,10 @@ __global__ void __launch_bounds__(256) splitk_reduce_kernel(const GemmArgs a, in
 }
 
 // column sums: out[n] = alpha * sum_m Y[m * ld + n].  One block per 64
-// columns: wave w adds rows w, w + 4, ... with lane = column (coalesced
-// 256-byte rows), the four partial sums meet in LDS.
+// columns: wave w adds rows w, w + 4, ... in that order, with lane = column
+// (coalesced 256-byte rows); the four partial sums meet in LDS.  The rows are
+// loaded 16 at a time ahead of their additions, so the loads' latencies
+// overlap while the order of the additions stays fixed.
 __global__ void __launch_bounds__(256) colsum_kernel(const float* __restrict__ Y, long M, long N, long ld,
                                                      float alpha, float* __restrict__ out)
 {
@@ -174,8 +197,18 @@ __global__ void __launch_bounds__(256) colsum_kernel(const float* __restrict__ Y
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const long n = (long)blockIdx.x * 64 + lane;
     double s = 0.0;
-    if (n < N)
-        for (long m = wv; m < M; m += 4) s += Y[m * ld + n];
+    if (n < N) {
+        constexpr int kAhead = 16;
+        long m = wv;
+        for (; m + 4 * (kAhead - 1) < M; m += 4 * kAhead) {
+            float v[kAhead];
+#pragma unroll
+            for (int j = 0; j < kAhead; ++j) v[j] = Y[(m + 4 * j) * ld + n];
+#pragma unroll
+            for (int j = 0; j < kAhead; ++j) s += v[j];
+        }
+        for (; m < M; m += 4) s += Y[m * ld + n];
+    }
     part[wv][lane] = s;
     __syncthreads();
     if (wv == 0 && n < N) out[n] = (float)(alpha * (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]));
@@ -309,7 +342,12 @@ __global__ void __launch_bounds__(256) mlp_target_grad_kernel(MlpGeo g, const ui
 
 // One wave per state: sample (k, a') from the masked softmax of z with the
 // uniform word u (inverse cumulative distribution in lane order of j), write
-// C' into states_new, the move and log q(k, a' | C).
+// C' into states_new, the move and log q(k, a' | C).  The state's logits are
+// read from HBM once, coalesced, into LDS (entry j at j + j/32, so that the
+// lanes' runs of 32 consecutive entries fall in distinct banks); every pass
+// reads them there.
+constexpr int kMaxD = 32 * 64;  // n T for n <= 32 pairs
+
 __global__ void __launch_bounds__(256) mlp_sample_kernel(MlpGeo g, const uint8_t* __restrict__ states,
                                                          const float* __restrict__ Z, int ldz,
                                                          const uint32_t* __restrict__ uword, int B,
@@ -317,15 +355,21 @@ __global__ void __launch_bounds__(256) mlp_sample_kernel(MlpGeo g, const uint8_t
                                                          int32_t* __restrict__ move_k, int32_t* __restrict__ move_old,
                                                          float* __restrict__ logq_fwd)
 {
+    __shared__ float zl_all[4][kMaxD + kMaxD / 32];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int t = blockIdx.x * 4 + wv;
     if (t >= B) return;
     const float* z = Z + (size_t)t * ldz;
+    float* zl = zl_all[wv];
     const int D = g.n * g.T;
+    for (int j = lane; j < D; j += 64) zl[j + (j >> 5)] = z[j];
+    // the wave's own LDS writes complete before any lane reads them
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     float zmax = -INFINITY;
     EntryWalk w1(lane, 64, g.T);
     for (int j = lane; j < D; j += 64, w1.next())
-        if (move_valid(g, w1.k, w1.c + 1)) zmax = fmaxf(zmax, z[j]);
+        if (move_valid(g, w1.k, w1.c + 1)) zmax = fmaxf(zmax, zl[j + (j >> 5)]);
     zmax = wave_max(zmax);
     // each lane owns a contiguous run of entries [lane*R, lane*R + R)
     const int R = (D + 63) / 64;
@@ -333,7 +377,7 @@ __global__ void __launch_bounds__(256) mlp_sample_kernel(MlpGeo g, const uint8_t
     EntryWalk w2(lane * R, 1, g.T);
     for (int i = 0; i < R; ++i, w2.next()) {
         const int j = lane * R + i;
-        if (j < D && move_valid(g, w2.k, w2.c + 1)) part += __expf(z[j] - zmax);
+        if (j < D && move_valid(g, w2.k, w2.c + 1)) part += __expf(zl[j + (j >> 5)] - zmax);
     }
     // exclusive prefix over lanes
     float incl = part;
@@ -356,7 +400,7 @@ __global__ void __launch_bounds__(256) mlp_sample_kernel(MlpGeo g, const uint8_t
             const int j = lane * R + i;
             if (j >= D || !move_valid(g, w3.k, w3.c + 1)) continue;
             last_valid = j;
-            c += __expf(z[j] - zmax);
+            c += __expf(zl[j + (j >> 5)] - zmax);
             if (c > target_mass) {
                 chosen = j;
                 break;
@@ -498,6 +542,13 @@ hipError_t launch_features(const MlpGeo& g, const uint8_t* states, const float* 
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s)
 {
     if (a.M <= 0 || a.N <= 0) return hipSuccess;
+    // the kernel indexes A and B with 32-bit offsets
+    auto span = [](long rows, long sr, long cols, long sc) {
+        return (rows - 1) * (sr < 0 ? -sr : sr) + (cols - 1) * (sc < 0 ? -sc : sc);
+    };
+    if (a.K > 0 && (span(a.M, a.sam, a.K, a.sak) >= (1L << 31) || span(a.K, a.sbk, a.N, a.sbn) >= (1L << 31) ||
+                    a.sam < 0 || a.sak < 0 || a.sbk < 0 || a.sbn < 0))
+        return hipErrorInvalidValue;
     const long tiles = ((a.N + kTile - 1) / kTile) * ((a.M + kTile - 1) / kTile);
     // split K when the tiles alone leave most of the 256 CUs idle and K is
     // long; the partials go to the workspace (splits x M x N floats)
