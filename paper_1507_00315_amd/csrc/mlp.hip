@@ -167,6 +167,90 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs a)
     }
 }
 
+// Large products with both operands contiguous along k (A[m, k] at m*sam + k,
+// B[k, n] at n*sbn + k: the forward passes X W^T): 128 x 64 output tiles,
+// each wave a 64 x 32 quarter as two MFMA blocks sharing their B operand,
+// operands loaded as float4 (the launcher checks K % 16 == 0, 16-byte
+// alignment and the 32-bit index range).  The MFMAs take the k pairs in the
+// same order as gemm_kernel's, so every output is bit-identical to it.
+constexpr int kBigM = 128, kBigN = 64;
+
+__global__ void __launch_bounds__(256) gemm_nt_kernel(const GemmArgs a)
+{
+    __shared__ float As[kTk][kBigM + 4];
+    __shared__ float Bs[kTk][kBigN + 4];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * kBigM, n0 = blockIdx.x * kBigN;
+    const int M = (int)a.M, N = (int)a.N, K = (int)a.K, sam = (int)a.sam, sbn = (int)a.sbn;
+    float16v acc[2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[bi][r] = 0.f;
+
+    // thread t loads k quad (t & 3) of A rows (t >> 2), (t >> 2) + 64 and of
+    // B column (t >> 2)
+    const int kq = tid & 3, rr = tid >> 2;
+    float4 pa[2], pb;
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int gm = min(m0 + rr + 64 * i, M - 1);
+            pa[i] = *reinterpret_cast<const float4*>(a.A + gm * sam + k0 + 4 * kq);
+        }
+        const int gn = min(n0 + rr, N - 1);
+        pb = *reinterpret_cast<const float4*>(a.B + gn * sbn + k0 + 4 * kq);
+    };
+    load(0);
+    for (int k0 = 0; k0 < K; k0 += kTk) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int row = rr + 64 * i;
+            const bool va = m0 + row < M;
+            As[4 * kq + 0][row] = va ? pa[i].x : 0.f;
+            As[4 * kq + 1][row] = va ? pa[i].y : 0.f;
+            As[4 * kq + 2][row] = va ? pa[i].z : 0.f;
+            As[4 * kq + 3][row] = va ? pa[i].w : 0.f;
+        }
+        {
+            const bool vb = n0 + rr < N;
+            Bs[4 * kq + 0][rr] = vb ? pb.x : 0.f;
+            Bs[4 * kq + 1][rr] = vb ? pb.y : 0.f;
+            Bs[4 * kq + 2][rr] = vb ? pb.z : 0.f;
+            Bs[4 * kq + 3][rr] = vb ? pb.w : 0.f;
+        }
+        __syncthreads();
+        if (k0 + kTk < K) load(k0 + kTk);
+#pragma unroll
+        for (int kk = 0; kk < kTk; kk += 2) {
+            const int kr = kk + (lane >> 5), c = lane & 31;
+            const float a0 = As[kr][wm * 64 + c], a1 = As[kr][wm * 64 + 32 + c];
+            const float b0 = Bs[kr][wn * 32 + c];
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int gm = m0 + wm * 64 + bi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int gn = n0 + wn * 32 + (lane & 31);
+            if (gm < M && gn < N) {
+                float v = a.alpha * acc[bi][r];
+                if (a.bias) v += a.bias[gn];
+                float* cp = a.C + (long)gm * a.scm + (long)gn * a.scn;
+                if (a.accumulate) v += *cp;
+                if (a.relu) v = v > 0.f ? v : 0.f;
+                if (a.relu_ref && !(a.relu_ref[(long)gm * a.scm + (long)gn * a.scn] > 0.f)) v = 0.f;
+                *cp = v;
+            }
+        }
+}
+
 // Sum of the split-K partials in z order (deterministic) and the epilogue of
 // gemm_kernel.
 __global__ void __launch_bounds__(256) splitk_reduce_kernel(const GemmArgs a, int splits)
@@ -552,6 +636,16 @@ hipError_t launch_gemm(const GemmArgs& a, hipStream_t s)
     const long tiles = ((a.N + kTile - 1) / kTile) * ((a.M + kTile - 1) / kTile);
     // split K when the tiles alone leave most of the 256 CUs idle and K is
     // long; the partials go to the workspace (splits x M x N floats)
+    // large products with both operands contiguous along k: 128 x 64 tiles
+    const long big_tiles = ((a.N + kBigN - 1) / kBigN) * ((a.M + kBigM - 1) / kBigM);
+    if (a.sak == 1 && a.sbk == 1 && a.K % kTk == 0 && a.sam % 4 == 0 && a.sbn % 4 == 0 &&
+        (reinterpret_cast<uintptr_t>(a.A) & 15) == 0 && (reinterpret_cast<uintptr_t>(a.B) & 15) == 0 &&
+        big_tiles >= 1024) {
+        hipLaunchKernelGGL(gemm_nt_kernel, dim3((unsigned)((a.N + kBigN - 1) / kBigN),
+                                                (unsigned)((a.M + kBigM - 1) / kBigM)),
+                           dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     int splits = 1;
     if (a.ws && tiles < 256 && a.K >= 8 * kTk) {
         const long by_occ = (512 + tiles - 1) / tiles, by_k = a.K / (4 * kTk);

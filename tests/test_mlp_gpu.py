@@ -85,6 +85,26 @@ def test_forward_matches_oracle(variant, n, h1, h2, B):
     assert err <= 2e-5 * max(scale, 1.0) * math.sqrt(max(h1, h2, g.din))
 
 
+def test_forward_large_batch_matches_oracle():
+    """A batch large enough for the 128 x 128-tile product (at least 1024
+    output tiles with both operands contiguous along k: the last layer over
+    8256 states, a ragged last row tile) against the fp64 oracle."""
+    variant, n, h1, h2, B = "skolem", 32, 256, 256, 8256
+    _say("mlp forward, large batch", variant, n, h1, h2, B)
+    g = OM.Geometry(n, variant)
+    rng = np.random.default_rng(47)
+    P = sk.mlp_init(n, variant, h1, h2, seed=9, scale=1.5)
+    S = random_states(g, B, rng)
+    betas = rng.uniform(0, 6, size=B)
+    z = sk.mlp_forward(n, variant, P, S, betas, h1, h2)
+    X = np.stack([OM.features(g, list(S[i]), betas[i]) for i in range(B)])
+    zo, _ = OM.forward(unpack(g, P, h1, h2), X)
+    scale = np.abs(zo).max()
+    err = np.abs(z - zo).max()
+    _say("  max |dz| =", err, "max |z| =", scale)
+    assert err <= 2e-5 * max(scale, 1.0) * math.sqrt(max(h1, h2, g.din))
+
+
 @pytest.mark.parametrize("variant,n,h1,h2,B", SHAPES)
 def test_loss_and_gradient_match_oracle(variant, n, h1, h2, B):
     _say("mlp grad", variant, n, h1, h2, B)
