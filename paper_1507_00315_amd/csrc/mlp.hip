@@ -9,6 +9,8 @@
 //                           a_k / T, per-pair collision flags, beta, E / 2n)
 //   * gemm_kernel           C = alpha * op(A) op(B) (+ bias, ReLU, ReLU mask,
 //                           accumulate), MFMA v_mfma_f32_32x32x2f32 on 64x64 tiles
+//   * gemm_nt_kernel        the same for large products whose operands are both
+//                           contiguous along k, on 128x64 tiles with float4 loads
 //   * colsum_kernel         bias gradients (column sums)
 //   * mlp_target_grad_kernel  masked softmax of the logits, heat-bath target,
 //                           cross-entropy and dL/dz = (q - p*) / B, one wave per state
