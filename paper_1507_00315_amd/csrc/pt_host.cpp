@@ -269,10 +269,13 @@ static sk_status pt_run_impl(const Relaxed& R, const sk_pt_params* p, hipStream_
             gpu_ms += before + train_ms;
             PT_HIP(hipEventRecord(D.e0, stream));
             net.free_batch();
-            PT_HIP(hipFree(D.pool));
-            PT_HIP(hipFree(D.pool_beta));
+            // both pointers cleared before any error is returned, so the
+            // destructor never frees them a second time
+            const hipError_t fa = hipFree(D.pool), fb = hipFree(D.pool_beta);
             D.pool = nullptr;
             D.pool_beta = nullptr;
+            PT_HIP(fa);
+            PT_HIP(fb);
         } else if (L->train_iterations > 0) {
             PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it + L->train_iterations, stream));
             it += L->train_iterations;
