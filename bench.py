@@ -67,6 +67,10 @@ MEASURED_TRAFFIC = {
     # (kernel, workload, log2 sign vectors per work item, waves per launch):
     #     (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
     ("exact_batch_kernel", "batch", 24, 4096): ("a519d991164ffec3", 3366.0, 6554.65625),
+    ("exact_batch_kernel", "batch", 24, 6144): ("a519d991164ffec3", 3371.625, 6619.375),
+    ("exact_batch_kernel", "batch", 24, 8192): ("a519d991164ffec3", 3356.3125, 6683.25),
+    ("exact_batch_kernel", "batch", 22, 6144): ("a519d991164ffec3", 11385.5, 25929.875),
+    ("exact_batch_kernel", "batch", 22, 8192): ("a519d991164ffec3", 11399.8125, 25992.53125),
     ("exact_v2_kernel", "s20", 25, 0): ("5996699165dbafe6", 158.5, 128.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0

@@ -788,15 +788,18 @@ static std::string tune_key(const std::vector<const Plan*>& plans)
 }
 
 // Times the batch on 1/16 of every instance for each candidate shape and
-// keeps the fastest (sign vectors per second).
+// keeps the fastest (sign vectors per second).  Candidates: 2^22 .. 2^28 sign
+// vectors per work item and 2 .. 8 persistent waves per SIMD.  Smaller work
+// items balance the tail of the launch better, but below 2^22 the host's
+// share (the work list and one residue row per item) outweighs the gain.
 static sk_status autotune(const std::vector<const Plan*>& plans, hipStream_t stream, int* best_lc,
                           uint64_t* best_w, double* best_rate)
 {
     DeviceCtx* ctx;
     sk_status s = device_ctx(&ctx);
     if (s != SK_OK) return s;
-    const int lcs[] = {24, 26, 28, 30};
-    const int wps[] = {1, 2, 3, 4};
+    const int lcs[] = {22, 24, 26, 28};
+    const int wps[] = {2, 4, 6, 8};
     double best = -1.0;
     for (int lc : lcs) {
         for (int wp : wps) {
