@@ -8,8 +8,12 @@ kernel launches, host CRT).  Prints one JSON line on stdout; progress goes to
 stderr.
 
 Workloads (all inputs are the problem statements themselves: no data files):
+  mixed  (the default) one step = the batch below in one persistent launch, then
+         the n = 24 slices: 8192 seeded chunks of 2^26 sign vectors of Skolem
+         n = 24 and of Langford n = 24 (two primes, the ones a full count uses),
+         16 rows of each checked against the oracle's stored recomputation
   batch  Skolem n = 16, 17, 20, 21; Langford n = 15, 16, 19, 20; hooked n = 14, 15
-         (the default: the mixed-instance run the metric's n = 20 figures come from)
+         (the mixed-instance run the metric's n = 20 figures come from)
   s24    Skolem n = 24, 2^47 sign vectors (the paper's single-GPU headline count)
   l24    Langford n = 24
   s20    Skolem n = 20;  l20  Langford n = 20
@@ -35,6 +39,8 @@ METRIC = "sign-vector terms/s for exact S(n),L(n) at n=20,24; PT rel. error vs G
 PEAK_LANE_OPS = 256 * 64 * 2.4e9  # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: VALU lane-instructions/s
 
 WORKLOADS = {
+    "mixed": [("skolem", 16), ("skolem", 17), ("skolem", 20), ("skolem", 21), ("langford", 15),
+              ("langford", 16), ("langford", 19), ("langford", 20), ("hooked", 14), ("hooked", 15)],
     "batch": [("skolem", 16), ("skolem", 17), ("skolem", 20), ("skolem", 21), ("langford", 15),
               ("langford", 16), ("langford", 19), ("langford", 20), ("hooked", 14), ("hooked", 15)],
     "s24": [("skolem", 24)],
@@ -142,11 +148,63 @@ def ring_ops_per_term(n: int, P: int) -> int:
     return n + P * (n - 1) + P
 
 
-def cpu_baseline(instances, threads):
-    """The CPU oracle's Gray-code partial sum, timed on a bounded slice of the
-    workload's largest instance (about 10-30 s of host work)."""
+def n24_slices():
+    """The n = 24 slices of the default step: for Skolem and Langford n = 24,
+    8192 seeded chunks of 2^26 sign vectors (of 2^21), with the two primes a
+    full count uses, and the rows the oracle recomputed for 16 of them
+    (tests/golden/big_chunks.json, written by tests/golden/make_big_chunks.py)."""
+    from paper_1507_00315_amd import inputs
+    with open(os.path.join(ROOT, "tests", "golden", "big_chunks.json")) as f:
+        g = json.load(f)
+    out = []
+    for v in ("skolem", "langford"):
+        c = g["cases"][f"{v}:24"]
+        seed = inputs.N24_SLICE_SEEDS[v]
+        ids = inputs.distinct_ids(seed, inputs.N24_CHUNK_BITS, inputs.N24_SLICE)
+        pos = {cid: i for i, cid in enumerate(ids)}
+        check = [(pos[ch["id"]], [int(x) for x in ch["residues"]]) for ch in c["chunks"]]
+        out.append({"variant": v, "seed": seed, "log2_chunks": inputs.N24_CHUNK_BITS, "ids": ids,
+                    "primes": [int(p) for p in g["primes"]], "check": check})
+    return out
+
+
+def host_threads():
+    """Threads the CPU baseline uses: the host cores this process may run on
+    (its affinity mask), capped by OMP_NUM_THREADS where the machine sets it
+    (a GPU machine gives one GPU's jobs a share of its cores that way)."""
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    return min(aff, int(omp)) if omp.isdigit() and int(omp) > 0 else aff
+
+
+def host_info():
+    info = {"cpu": cpu_model(), "os_cpu_count": os.cpu_count(),
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        import subprocess
+        info["nproc"] = int(subprocess.run(["nproc"], capture_output=True, text=True, timeout=10).stdout.strip())
+        info["nproc_all"] = int(subprocess.run(["nproc", "--all"], capture_output=True, text=True,
+                                               timeout=10).stdout.strip())
+    except Exception:  # nproc missing: the counts above remain
+        pass
+    return info
+
+
+def cpu_baseline(instances):
+    """The CPU oracle as it stands, on the GPU machine's host cores: its Gray-code
+    partial sum on a bounded slice of the workload's largest instance (about
+    10-30 s of host work), and its backtracking count (the plain definition,
+    largest difference first) of S(12) and S(13)."""
     import oracle as O
     O.build(force=False)
+    threads = host_threads()
     variant, n = max(instances, key=lambda vn: vn[1])
     pos, _ = O.instance(n, variant)
     free_bits = 32 if n >= 20 else 28
@@ -158,10 +216,18 @@ def cpu_baseline(instances, threads):
     t0 = time.time()
     O.chunk_partial(n, variant, fixed, p, "gray", threads=threads)
     dt = time.time() - t0
-    return {"value": terms / dt, "unit": "terms/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+    bt = []
+    for bn in (12, 13):
+        t1 = time.time()
+        c = O.count_backtrack(bn, "skolem", threads=threads)
+        d1 = time.time() - t1
+        bt.append({"instance": f"skolem:{bn}", "ordered_count": c, "seconds": d1, "solutions_per_s": c / d1,
+                   "threads": threads})
+    return {"value": terms / dt, "unit": "terms/s", "cores": threads, "kind": "oracle", "host": host_info(),
             "sample": f"{variant} n={n}: Gray-code partial sum over 2^{len(pos) - len(fixed)} sign vectors "
                       f"(x at positions above {pos[free_bits]} fixed), one prime, {threads} threads, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "backtracking": bt}
 
 
 def config5_ladder():
@@ -251,7 +317,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batch", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="mixed", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--log2-chunk", type=int, default=0)
     ap.add_argument("--kernel", type=int, default=0)
@@ -313,12 +379,23 @@ def main():
     tuning = {"log2_chunk_terms": args.log2_chunk, "kernel": args.kernel, "waves_per_launch": args.waves}
     if args.workload == "s12":
         tuning["primes"] = 2
+    batched = args.workload in ("batch", "mixed") and not args.separate
 
     slice_ids = None
     if args.workload == "l28slice":
         from paper_1507_00315_amd import inputs
         slice_ids = inputs.distinct_ids(inputs.SLICE_SEED, L28_CHUNK_BITS, L28_SLICE)
         slice_primes = sk.describe(28, "langford")["primes"]  # default primes, as a full count uses
+    n24 = n24_slices() if args.workload == "mixed" else []
+
+    def run_slice(tag, sl):
+        """One n = 24 slice: 8192 chunks in one call; the rows the oracle
+        recomputed must match."""
+        rows, st = sk.partial_chunks(24, sl["variant"], sl["log2_chunks"], sl["ids"], sl["primes"], with_stats=True)
+        ok = all(rows[i] == want_row for i, want_row in sl["check"])
+        log(f"[{tag}] {sl['variant']} n=24 slice: kernel {st['kernel_ms']:.1f} ms "
+            f"{st['terms'] / max(st['kernel_ms'], 1e-9) * 1e3:.3e} terms/s  check={ok}")
+        return (sl["variant"], 24, None, st, ok)
 
     def step(tag):
         res = []
@@ -331,15 +408,18 @@ def main():
             log(f"[{tag}] l28 slice: {len(rows)} chunks, kernel {st['kernel_ms']:.1f} ms "
                 f"{st['terms'] / max(st['kernel_ms'], 1e-9) * 1e3:.3e} terms/s  wall {time.time() - t0:.1f} s")
             return res
-        if args.workload == "batch" and not args.separate:
+        if batched:
             counts, st = sk.count_batch([(n, v, sk.ORDERED if v == "hooked" else 0) for v, n in instances],
                                         tuning=tuning if args.log2_chunk else None)
+            checks = []
             for (v, n), c in zip(instances, counts):
                 ok = want.get((v, n))
-                res.append((v, n, c, None, None if ok is None else (ok == c)))
-            res.append(("*", 0, 0, st, None))
+                checks.append(None if ok is None else (ok == c))
+            res.append(("*", 0, counts, st, all(x is not False for x in checks)))
             log(f"[{tag}] batch: kernel {st['kernel_ms']:.1f} ms  {st['terms'] / max(st['kernel_ms'], 1e-9) * 1e3:.3e}"
-                f" terms/s  launches {st['launches']}  checks {[r[4] for r in res[:-1]]}")
+                f" terms/s  launches {st['launches']}  checks {checks}")
+            for sl in n24:
+                res.append(run_slice(tag, sl))
             return res
         last = [time.time()]
 
@@ -359,7 +439,7 @@ def main():
         return res
 
     launch_waves = args.waves
-    if args.workload == "batch" and not args.separate and not args.no_autotune and not args.log2_chunk:
+    if batched and not args.no_autotune and not args.log2_chunk:
         t0 = time.time()
         best, rate = sk.autotune_batch([(n, v) for v, n in instances])
         launch_waves = best["waves_per_launch"]
@@ -374,39 +454,101 @@ def main():
     sync()
     elapsed = time.perf_counter() - t0
 
-    def stats_of(st):
-        return [r[3] for r in st if r[3] is not None]
-
-    terms_per_step = sum(s["terms"] for s in stats_of(results[0]))
+    terms_per_step = sum(r[3]["terms"] for r in results[0])
     total_terms = terms_per_step * args.steps
     value = total_terms / elapsed
     all_ok = all(r[4] is not False for st in results for r in st)
 
-    # Roofline of the exact kernel: VALU instructions per sign vector (design
-    # count of the tuned body) x sign vectors / launch durations measured with
-    # HIP events on the launch stream.
-    instr = 0.0
-    ring = 0.0
-    for v, n in instances:
+    # Per kernel: VALU instructions per sign vector (design count of the tuned
+    # body) x sign vectors / launch durations measured with HIP events on the
+    # launch stream.
+    def design_instr(v, n, symmetric_terms):
         d = sk.describe(n, v)
         d["primes_used"] = d["primes"]
-        instr_per = valu_per_term(d)
-        # sign vectors the kernel evaluates: half of 2^(2n-1) where Lemma 2.4
-        # applies, and of those 1/2 + 2^-(r+1) with r reversal quadruples
-        if slice_ids is not None:
-            terms_inst = terms_per_step
+        per = valu_per_term(d)
+        if symmetric_terms:
+            r = d["reversal_quads"] if results[0][0][3]["reversal_quads"] else 0
+            terms = ((1 << (2 * n - 1)) >> d["symmetric"]) // 2 ** (r + 1) * (2 ** r + 1)
         else:
-            r = d["reversal_quads"] if stats_of(results[0])[0]["reversal_quads"] else 0
-            terms_inst = ((1 << (2 * n - 1)) >> d["symmetric"]) // 2 ** (r + 1) * (2 ** r + 1)
-        instr += terms_inst * instr_per
-        ring += terms_inst * ring_ops_per_term(n, d["primes"])
-    kms = sum(s["kernel_ms"] for st in results for s in stats_of(st)) / args.steps
-    launches = sum(s["launches"] for st in results for s in stats_of(st)) // args.steps
-    achieved = instr / (kms * 1e-3) if kms > 0 else 0.0
-    kernel_name = sk.kernel_name(stats_of(results[0])[0]["kernel_variant"])
-    instr_per_term = instr / terms_per_step
+            terms = None
+        return per, terms, ring_ops_per_term(n, d["primes"])
 
-    covered = terms_per_step if slice_ids is not None else sum(1 << (2 * n - 1) for v, n in instances)
+    legs = []  # (name, kernel, terms per step, VALU instr per step, ring ops per step, results index)
+    if slice_ids is not None:
+        per, _, ring = design_instr("langford", 28, False)
+        legs.append(("langford:28 slice", sk.kernel_name(results[0][0][3]["kernel_variant"]), terms_per_step,
+                     per * terms_per_step, ring * terms_per_step, 0))
+    elif batched:
+        instr = ring = 0
+        for v, n in instances:
+            per, terms, rg = design_instr(v, n, True)
+            instr += per * terms
+            ring += rg * terms
+        legs.append(("batch", "exact_batch_kernel", results[0][0][3]["terms"], instr, ring, 0))
+        for i, sl in enumerate(n24):
+            per, _, rg = design_instr(sl["variant"], 24, False)
+            t = results[0][1 + i][3]["terms"]
+            legs.append((f"{sl['variant']}:24 slice", f"exact_v2_kernel<{sk.VARIANTS[sl['variant']]},24>", t,
+                         per * t, rg * t, 1 + i))
+    else:
+        for i, (v, n) in enumerate(instances):
+            per, terms, rg = design_instr(v, n, True)
+            t = results[0][i][3]["terms"]
+            legs.append((f"{v}:{n}", sk.kernel_name(results[0][i][3]["kernel_variant"]), t, per * t, rg * t, i))
+
+    rooflines = []
+    for name, kernel, terms, instr, ring, idx in legs:
+        kms = sum(st[idx][3]["kernel_ms"] for st in results) / args.steps
+        launches = sum(st[idx][3]["launches"] for st in results) // args.steps
+        sec = kms * 1e-3
+        rooflines.append({"leg": name, "kernel": kernel, "bound": "alu", "unit": "VALU lane-instr/s",
+                          "achieved": instr / sec if sec > 0 else 0.0, "peak": PEAK_LANE_OPS,
+                          "frac": instr / sec / PEAK_LANE_OPS if sec > 0 else 0.0,
+                          "valu_instr_per_term": instr / terms, "terms_per_launch_step": terms,
+                          "terms_per_s_kernel": terms / sec if sec > 0 else 0.0, "kernel_ms_per_step": kms,
+                          "launches": launches, "avg_launch_ms": kms / max(launches, 1),
+                          "ring_ops_per_term": ring / terms})
+    # the dominant kernel: the single kernel with the largest time per step
+    dom = max(rooflines, key=lambda r: r["avg_launch_ms"])
+    st0 = results[0][0][3]
+    log2_chunk = st0["log2_chunk_terms"]
+    roofline = {"bound": "alu", "achieved": dom["achieved"], "peak": PEAK_LANE_OPS, "unit": "VALU lane-instr/s",
+                "frac": dom["frac"],
+                "traffic": traffic_per_launch(dom["kernel"].split("<")[0], "batch" if args.workload == "mixed"
+                                              else args.workload, log2_chunk, launch_waves),
+                "kernel": dom["kernel"], "leg": dom["leg"], "valu_instr_per_term": dom["valu_instr_per_term"],
+                "terms_per_s_kernel": dom["terms_per_s_kernel"], "launches": dom["launches"],
+                "avg_launch_ms": dom["avg_launch_ms"],
+                "note": "achieved = design VALU instructions per sign vector x sign vectors / kernel time; the "
+                        "method's ring-operation count per term (ring_ops_per_term) is not an issue roof: "
+                        "packed 16-bit adds, scalar-unit pair-sum updates and products shared across primes "
+                        "do several ring operations per VALU lane-instruction"}
+
+    covered = 0
+    if slice_ids is not None:
+        covered = terms_per_step
+    elif batched:
+        covered = sum(1 << (2 * n - 1) for v, n in instances) + sum(results[0][1 + i][3]["terms"]
+                                                                     for i in range(len(n24)))
+    else:
+        covered = sum(1 << (2 * n - 1) for v, n in instances)
+    config = {"workload": args.workload,
+              "instances": [f"{v}:{n}" for v, n in instances],
+              "terms_per_step": terms_per_step,
+              "primes_per_instance": {f"{v}:{n}": sk.describe(n, v)["primes"] for v, n in instances},
+              "log2_chunk_terms": log2_chunk,
+              "waves_per_launch": launch_waves,
+              "lemma_2_4_halving": bool(st0.get("symmetry_halved")),
+              "sign_vectors_covered_per_step": covered,
+              "sign_vectors_covered_per_s": covered * args.steps / elapsed,
+              "reversal_quads": st0.get("reversal_quads", 0),
+              "results_match_expected": all_ok}
+    if n24:
+        config["n24_slices"] = [{"instance": f"{sl['variant']}:24", "chunks": len(sl["ids"]),
+                                 "of_chunks": 1 << sl["log2_chunks"],
+                                 "sign_vectors_per_chunk": 1 << (47 - sl["log2_chunks"]), "seed": sl["seed"],
+                                 "primes": len(sl["primes"]), "rows_checked_per_step": len(sl["check"])}
+                                for sl in n24]
     line = {
         "metric": METRIC,
         "value": value,
@@ -420,44 +562,27 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload,
-                   "instances": [f"{v}:{n}" for v, n in instances],
-                   "terms_per_step": terms_per_step,
-                   "primes_per_instance": {f"{v}:{n}": sk.describe(n, v)["primes"] for v, n in instances},
-                   "log2_chunk_terms": stats_of(results[0])[0]["log2_chunk_terms"],
-                   "waves_per_launch": launch_waves,
-                   "lemma_2_4_halving": bool(stats_of(results[0])[0].get("symmetry_halved")),
-                   "sign_vectors_covered_per_step": covered,
-                   "sign_vectors_covered_per_s": covered * args.steps / elapsed,
-                   "reversal_quads": stats_of(results[0])[0].get("reversal_quads", 0),
-                   "results_match_expected": all_ok},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS, "unit": "VALU lane-instr/s",
-                     "frac": achieved / PEAK_LANE_OPS, "traffic": traffic_per_launch(kernel_name, args.workload,
-                                                               stats_of(results[0])[0]["log2_chunk_terms"],
-                                                               launch_waves),
-                     "kernel": kernel_name,
-                     "valu_instr_per_term": instr_per_term, "terms_per_s_kernel": terms_per_step / (kms * 1e-3),
-                     "launches": launches, "avg_launch_ms": kms / max(launches, 1),
-                     "ring_ops_per_term": ring / terms_per_step,
-                     "ring_ops_per_s": ring / (kms * 1e-3) if kms > 0 else 0.0},
+        "config": config,
+        "roofline": roofline,
+        "rooflines": rooflines,
     }
     if slice_ids is not None:
         full_chunks = 1 << L28_CHUNK_BITS
+        kms = rooflines[0]["kernel_ms_per_step"]
         line["config"]["slice"] = {"chunks": len(slice_ids), "of_chunks": full_chunks,
                                    "terms_per_chunk": terms_per_step // len(slice_ids), "seed": 1507,
                                    "projected_full_count_s": kms * 1e-3 * full_chunks / len(slice_ids),
                                    "projected_full_count_wall_s": elapsed / args.steps * full_chunks / len(slice_ids)}
-    if args.workload == "batch" and not args.no_pt:
+    if batched and not args.no_pt:
         learned_cfg = dict(hidden1=256, hidden2=256, first_level=args.pt_learned_first,
                            plain_per_learned=args.pt_learned_every, snapshots=8, train_steps=400, minibatch=1024,
                            lr=1e-3, init_seed=1)
         line["pt"] = pt_bench(sk, want, [1 << int(x) for x in args.pt_plain_log2.split(",")],
-                              [1 << int(x) for x in args.pt_learned_log2.split(",")], args.pt_ladders, learned_cfg,
-                              cpu_pt=not args.no_cpu_baseline)
+                              [1 << int(x) for x in args.pt_learned_log2.split(",") if x], args.pt_ladders,
+                              learned_cfg, cpu_pt=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
         log("cpu baseline ...")
-        line["cpu_baseline"] = cpu_baseline(instances, threads)
+        line["cpu_baseline"] = cpu_baseline(instances)
     print(json.dumps(line), flush=True)
     if not all_ok:
         sys.exit(1)

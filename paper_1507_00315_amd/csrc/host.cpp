@@ -805,9 +805,13 @@ static sk_status autotune(const std::vector<const Plan*>& plans, hipStream_t str
         for (int wp : wps) {
             std::vector<BatchJob> jobs;
             for (auto* p : plans) {
+                // the same work per item as the production batch: Lemma 2.4
+                // half and reversal weights (weight-0 jobs skipped in a chunk)
                 BatchJob j;
                 j.plan = p;
                 j.primes = default_primes(primes_for(p->n), 0);
+                j.half = hat_symmetric(*p);
+                j.reverse = true;
                 jobs.push_back(j);
             }
             sk_stats st;

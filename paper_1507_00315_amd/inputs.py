@@ -67,3 +67,16 @@ def subset(seed: int, items: List[int], count: int) -> List[int]:
 # Config of the frontier slice: Langford n = 28, chunks of 2^31 sign vectors,
 # 4096 chunks of the 2^24 drawn with this seed; 16 of them recomputed on the CPU.
 SLICE_SEED = 1507
+
+# Slices of the n = 24 counts timed beside the mixed-instance launch: 8192 of
+# the 2^21 chunks of 2^26 sign vectors of Skolem n = 24 and of Langford n = 24,
+# drawn with these seeds; 16 chunks of each (seed + 1) are recomputed on the CPU.
+N24_SLICE_SEEDS = {"skolem": 2424, "langford": 2425}
+N24_CHUNK_BITS = 21
+N24_SLICE = 8192
+
+# Chunks of Skolem n = 25 (2^21 chunks of 2^28 sign vectors) recomputed on the
+# CPU for the parity of the n = 25 kernel: 8 ids drawn with this seed.
+S25_SEED = 2525
+S25_CHUNK_BITS = 21
+S25_CHUNKS = 8

@@ -1,0 +1,103 @@
+"""GPU parity of the exact path at n = 22..25 (the configurations the
+benchmark's n = 24 figures and the largest single-GPU counts come from).
+
+* L(23), S(24) and L(24) as full counts against the printed values (Table 4,
+  Tables 7 and 8), reported and ordered; with every count n <= 21 checked in
+  tests/test_exact_gpu.py this covers every nonzero S(n), L(n) with n <= 24.
+* S(22) and L(22) with the existence shortcut off: the evaluated sum must
+  vanish (Sec. 1.1).
+* Per-chunk residues of S(24), L(24) (2^26 sign vectors per chunk, in the
+  8192-chunk launch the benchmark times) and S(25) (2^28 per chunk, the n = 25
+  kernel) against the oracle's recomputation stored by
+  tests/golden/make_big_chunks.py.
+"""
+import json
+import os
+import sys
+
+import pytest
+
+import paper_1507_00315_amd as sk
+from paper_1507_00315_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _ready():
+    sk.lib()
+
+
+@pytest.mark.parametrize("variant,n", [("langford", 23), ("skolem", 24), ("langford", 24)])
+def test_printed_counts_n23_n24(variant, n):
+    """Full exact counts with both symmetries (Lemma 2.3, Lemma 2.4) against
+    the printed values; the ordered count is twice the printed one (Sec. 1.3)
+    and, where Table 4 prints it, equal to that column."""
+    paper = _load("paper_counts.json")
+    want = int(paper[variant][str(n)])
+    _say("full count", variant, n)
+    r = sk.count_ex(n, variant, ordered=True)
+    _say(f"  {r.count}  kernel {r.stats['kernel_ms'] / 1e3:.1f} s  body {r.stats['kernel_variant']}")
+    assert r.stats["kernel_variant"] == 2  # the tuned body for this n
+    assert r.count == 2 * want
+    ordered = paper.get(f"{variant}_ordered", {}).get(str(n))
+    if ordered is not None:
+        assert r.count == int(ordered)
+
+
+@pytest.mark.parametrize("variant", ["skolem", "langford"])
+def test_nonexistent_n22_sum_vanishes(variant):
+    """n = 22 has no Skolem (n = 2 mod 4) and no Langford (n = 2 mod 4)
+    pairing; with the shortcut off the whole signed sum is evaluated."""
+    _say("zero", variant, 22)
+    r = sk.count_ex(22, variant, ordered=True, no_shortcut=True)
+    assert r.count == 0
+    assert r.stats["terms"] > 0 and r.stats["symmetry_halved"] == 0
+
+
+def _case(key):
+    g = _load("big_chunks.json")
+    return g["primes"], g["cases"][key]
+
+
+@pytest.mark.parametrize("variant", ["skolem", "langford"])
+def test_n24_slice_chunks_match_oracle(variant):
+    """The benchmark's n = 24 slice: 8192 chunks of 2^26 sign vectors in one
+    call, in its launch shape; the 16 chunks the oracle recomputed must match
+    bit for bit, and repeating the call gives the same rows."""
+    primes, c = _case(f"{variant}:24")
+    ids = inputs.distinct_ids(c["slice_seed"], c["log2_chunks"], c["slice_size"])
+    assert c["slice_size"] == inputs.N24_SLICE and c["log2_chunks"] == inputs.N24_CHUNK_BITS
+    rows, st = sk.partial_chunks(24, variant, c["log2_chunks"], ids, primes, with_stats=True)
+    _say(f"{variant} 24 slice: {st['kernel_ms']:.1f} ms, body {st['kernel_variant']}")
+    assert st["kernel_variant"] == 2 and st["terms"] == len(ids) << 26
+    pos = {cid: i for i, cid in enumerate(ids)}
+    for ch in c["chunks"]:
+        assert rows[pos[ch["id"]]] == [int(x) for x in ch["residues"]], ch["id"]
+    again = sk.partial_chunks(24, variant, c["log2_chunks"], ids, primes)
+    assert again == rows
+
+
+def test_s25_chunks_match_oracle():
+    """The n = 25 kernel (two primes cover 25!; Sec. 2.2's split into
+    independent parts) on 8 chunks of 2^28 sign vectors."""
+    primes, c = _case("skolem:25")
+    ids = [ch["id"] for ch in c["chunks"]]
+    assert ids == inputs.distinct_ids(inputs.S25_SEED, inputs.S25_CHUNK_BITS, inputs.S25_CHUNKS)
+    rows, st = sk.partial_chunks(25, "skolem", c["log2_chunks"], ids, primes, with_stats=True)
+    assert st["kernel_variant"] == 2
+    for ch, row in zip(c["chunks"], rows):
+        assert row == [int(x) for x in ch["residues"]], ch["id"]
+    ref = sk.partial_chunks(25, "skolem", c["log2_chunks"], ids[:2], primes, tuning={"kernel": 1})
+    assert ref == rows[:2]

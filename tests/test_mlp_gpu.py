@@ -105,8 +105,61 @@ def test_forward_large_batch_matches_oracle():
     assert err <= 2e-5 * max(scale, 1.0) * math.sqrt(max(h1, h2, g.din))
 
 
+U32 = 2.0 ** -24  # unit roundoff of fp32
+
+
+def grad_error_bound(Pd, g: OM.Geometry, states, betas, lam=None):
+    """Element-wise bound on the fp32 gradient's distance from the fp64 one.
+
+    The gradient is a chain of dot products (backward through three layers,
+    each a sum over the batch).  A length-K fp32 dot product has error at most
+    K u sum |x_i y_i| (u = 2^-24; the worst case, lam=None), or with
+    probability at least 1 - 2 exp(-lam^2 / 2) at most lam sqrt(K) u sum |x_i y_i|
+    when the rounding errors are independent (Higham and Mary, SIAM J. Sci.
+    Comput. 2019; lam=6).  Errors already in a product's inputs enter the same
+    sum of absolute products.  So every gradient entry is bounded by
+    c e(K_chain) M, where M is the same backward pass run on absolute values
+    (|W|, |h|, and |dz| replaced by (q + p*) / B, which bounds dz = (q - p*) / B,
+    with q widened by the relative change the logits' own fp32 error causes),
+    K_chain the sum of the contraction lengths on the path plus the forward
+    pass's, and ReLU masks widened to pre-activations within the forward
+    error of zero, where fp32 may take the other branch.
+    Returns {name: bound array}."""
+    def e(K):
+        return K * U32 if lam is None else lam * math.sqrt(K) * U32
+
+    X = np.stack([OM.features(g, list(a), b) for a, b in zip(states, betas)])
+    Tg = np.stack([OM.target(g, list(a), b) for a, b in zip(states, betas)])
+    mask = np.broadcast_to(g.valid.reshape(-1), (len(states), g.dout))
+    z, c = OM.forward(Pd, X)
+    q = np.where(mask, np.exp(OM.masked_log_softmax(z, mask)), 0.0)
+    B = len(states)
+    h1, h2 = Pd["W1"].shape[0], Pd["W2"].shape[0]
+    A = {k: np.abs(v) for k, v in Pd.items()}
+    a1_abs = np.abs(X) @ A["W1"].T + A["b1"]
+    a2_abs = np.maximum(a1_abs, 0) @ A["W2"].T + A["b2"]
+    z_abs = np.maximum(a2_abs, 0) @ A["W3"].T + A["b3"]
+    k_fwd = g.din + h1 + h2
+    k_chain = B + g.dout + h2 + h1 + k_fwd
+    # the logits' error (per state, the largest) moves q by at most twice it, relative to q
+    zq = 2 * e(k_fwd) * z_abs.max(axis=1, keepdims=True)
+    dzA = (q * (1 + zq / e(k_chain)) + Tg) / B
+    w1 = c["a1"] > -2 * e(k_fwd) * a1_abs
+    w2 = c["a2"] > -2 * e(k_fwd) * a2_abs
+    M = {"W3": dzA.T @ np.abs(c["h2"]), "b3": dzA.sum(0)}
+    d2 = (dzA @ A["W3"]) * w2
+    M["W2"] = d2.T @ np.abs(c["h1"])
+    M["b2"] = d2.sum(0)
+    d1 = (d2 @ A["W2"]) * w1
+    M["W1"] = d1.T @ np.abs(X)
+    M["b1"] = d1.sum(0)
+    return {k: 4 * e(k_chain) * v for k, v in M.items()}
+
+
 @pytest.mark.parametrize("variant,n,h1,h2,B", SHAPES)
 def test_loss_and_gradient_match_oracle(variant, n, h1, h2, B):
+    """Loss and every gradient entry against the fp64 oracle, each entry
+    within the bound of grad_error_bound."""
     _say("mlp grad", variant, n, h1, h2, B)
     g = OM.Geometry(n, variant)
     rng = np.random.default_rng(21 + n)
@@ -114,18 +167,27 @@ def test_loss_and_gradient_match_oracle(variant, n, h1, h2, B):
     S = random_states(g, B, rng)
     betas = rng.uniform(0, 4, size=B)
     loss, grad = sk.mlp_loss_grad(n, variant, P, S, betas, h1, h2)
-    lo, go = OM.loss_and_grad(unpack(g, P, h1, h2), g, [list(s) for s in S], list(betas))
+    Pd = unpack(g, P, h1, h2)
+    lo, go = OM.loss_and_grad(Pd, g, [list(s) for s in S], list(betas))
     _say("  loss", loss, lo)
     assert abs(loss - lo) <= 1e-5 * max(1.0, abs(lo)) * 10
     gg = unpack(g, grad, h1, h2)
+    bound = grad_error_bound(Pd, g, S, betas)
     for k in go:
-        ref = go[k]
-        rel = np.linalg.norm(gg[k] - ref) / max(np.linalg.norm(ref), 1e-12)
-        _say("  grad", k, "relative error", rel)
-        assert rel < 2e-4, k
+        err = np.abs(gg[k] - go[k])
+        _say(f"  grad {k}: max |err| {err.max():.3e}, max err/bound {np.max(err / (bound[k] + 1e-300)):.3e}")
+        assert np.all(err <= bound[k] + 1e-30), k
 
 
 def test_adam_training_matches_oracle():
+    """Adam steps on the GPU against the fp64 oracle, entry by entry.  An
+    Adam step moves an entry by lr r with r = m^/(sqrt(v^) + eps), a ratio of
+    degree 0 in the gradients (|r| <= 2 over these few steps), so gradients
+    known to within relative error rho (grad_error_bound with lam = 6, over
+    |g|) move r by at most rho (2 + |r|) <= 4 rho; entries whose gradient may
+    change sign within that bound in some step (rho >= 1/4) may move by
+    anything Adam allows, at most 3 lr per step.  fp32 storage of the
+    parameters adds 2 u |P| per step."""
     n, variant, h1, h2 = 6, "skolem", 48, 40
     g = OM.Geometry(n, variant)
     rng = np.random.default_rng(7)
@@ -138,21 +200,33 @@ def test_adam_training_matches_oracle():
     Pd = unpack(g, P0, h1, h2)
     M = {k: np.zeros_like(v) for k, v in Pd.items()}
     V = {k: np.zeros_like(v) for k, v in Pd.items()}
+    rel = {k: np.zeros_like(v) for k, v in Pd.items()}
     lo = None
     for t in range(steps):
         rows = [(t * B + i) % N for i in range(B)]
-        lo, G = OM.loss_and_grad(Pd, g, [list(S[r]) for r in rows], [betas[r] for r in rows])
+        st = [list(S[r]) for r in rows]
+        bt = [betas[r] for r in rows]
+        bnd = grad_error_bound(Pd, g, st, bt, lam=6.0)
+        lo, G = OM.loss_and_grad(Pd, g, st, bt)
+        for k in G:
+            rel[k] = np.maximum(rel[k], bnd[k] / np.maximum(np.abs(G[k]), 1e-300))
         OM.adam(Pd, G, M, V, t + 1, lr=lr)
-    ref = pack(Pd)
-    d = np.abs(P1.astype(np.float64) - ref.astype(np.float64))
-    moved = np.abs(ref.astype(np.float64) - P0.astype(np.float64))
-    _say("adam: loss", last, lo, "median diff", np.median(d), "max diff", d.max(), "median move", np.median(moved))
     assert abs(last - lo) < 1e-4 * max(1.0, abs(lo))
-    # Adam moves each weight by about lr per step; fp32 vs fp64 may flip the
-    # sign of a near-zero gradient, so compare the bulk, and bound the rest
-    assert np.median(d) < 1e-3 * lr
-    assert np.mean(d > 0.1 * lr) < 0.01
-    assert d.max() <= 2 * lr * steps + 1e-6
+    got = unpack(g, P1, h1, h2)
+    start = unpack(g, P0, h1, h2)
+    flipped = 0
+    for k in Pd:
+        r = rel[k]
+        stable = r < 0.25
+        tol = np.where(stable, steps * lr * 4 * r, 3 * lr * steps)
+        tol = tol + steps * U32 * (np.abs(start[k]) + lr * steps) * 2
+        err = np.abs(got[k] - Pd[k])
+        flipped += int((~stable).sum())
+        _say(f"adam {k}: max |err| {err.max():.3e}, max err/tol {np.max(err / tol):.3e}, "
+             f"unstable entries {int((~stable).sum())} of {r.size}")
+        assert np.all(err <= tol), k
+    # most entries are held to the tight bound
+    assert flipped < 0.25 * sum(v.size for v in Pd.values())
 
 
 def _oracle_decision(Pd, g, a, beta, wp, wa):
