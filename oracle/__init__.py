@@ -19,6 +19,10 @@ What is here, and the passage of arXiv 1507.00315 each part follows:
   sum over all of {+1,-1}^P with exact Python integers, divided by 2^|P|.
 * ``chunk_partial``       -- the signed sum of Lemma 2.1 over the sign vectors that
   agree with a fixed partial assignment, modulo p (C; plain or Gray-code order).
+* ``larsen_literal``, ``larsen_partial``, ``larsen_count`` -- the inclusion-
+  exclusion count of Sec. 2 (third approach: placements avoiding positions),
+  literally with exact integers (tiny n) and modulo p in C, each term from
+  scratch.
 * ``skolem_construction`` / ``davies_construction`` -- Tables 1 and 2.
 * ``reported``            -- the counting conventions of Sec. 1.3 (reflections
   counted once for n > 1).
@@ -91,6 +95,9 @@ def lib():
         u32p = ctypes.POINTER(ctypes.c_uint32)
         u64p = ctypes.POINTER(ctypes.c_uint64)
         ip = ctypes.POINTER(ctypes.c_int)
+        L.orc_larsen_partial.restype = ctypes.c_uint64
+        L.orc_larsen_partial.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.c_uint64, ctypes.c_int]
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.orc_philox4x32_10.restype = None
         L.orc_energy_histogram.argtypes = [ctypes.c_int, ctypes.c_int, u64p]
@@ -270,6 +277,52 @@ def chunk_partial(n: int, variant, fixed: Dict[int, int], p: int, method: str = 
     if method == "gray":
         return int(lib().orc_chunk_partial_gray(n, v, mask, neg, p, threads))
     raise ValueError(method)
+
+
+# --------------------------------------------------------------------------
+# Inclusion-exclusion (Sec. 2, the third approach)
+# --------------------------------------------------------------------------
+
+def larsen_literal(n: int, variant) -> int:
+    """Ordered count by inclusion-exclusion over the positions left empty,
+    with exact integers: the universe is every placement of the pairs inside
+    P with overlaps allowed, A_i those leaving position i empty, and the
+    pairings are the placements in no A_i, so
+    C = sum over S subset of P of (-1)^|S| prod_k N_k(P minus S), N_k(T) being
+    the number of a with a, a + d_k in T.  Exponential: use |P| <= 16."""
+    pos, d = instance(n, variant)
+    m = len(pos)
+    total = 0
+    for bits in range(1 << m):
+        T = {pos[i] for i in range(m) if not (bits >> i) & 1}
+        prod = 1
+        for dk in d:
+            prod *= sum(1 for a in T if a + dk in T)
+            if prod == 0:
+                break
+        total += -prod if bin(bits).count("1") % 2 else prod
+    return total
+
+
+def larsen_partial(n: int, variant, fixed: Dict[int, int], p: int, threads: int = 1) -> int:
+    """Residue in [0, p) of the inclusion-exclusion sum restricted to the sets
+    S that agree with ``fixed`` ({position: 1 if the position is occupied
+    (not in S), 0 if it is in S}), each term evaluated from scratch (C)."""
+    mask = 0
+    empty = 0
+    for q, val in fixed.items():
+        if val not in (0, 1):
+            raise ValueError("fixed values are 0 (in S) or 1 (not in S)")
+        mask |= 1 << (q - 1)
+        if val == 0:
+            empty |= 1 << (q - 1)
+    return int(lib().orc_larsen_partial(n, _variant(variant), mask, empty, p, threads))
+
+
+def larsen_count(n: int, variant, p: int, threads: int = 1) -> int:
+    """The whole inclusion-exclusion sum modulo p (the ordered count when
+    p exceeds it)."""
+    return larsen_partial(n, variant, {}, p, threads)
 
 
 # --------------------------------------------------------------------------

@@ -339,3 +339,102 @@ uint64_t orc_chunk_partial_gray(int n, int variant, uint64_t fixed_mask, uint64_
     pthread_mutex_destroy(&G.lock);
     return G.acc;
 }
+
+/* ------------------------------------------------------------------ */
+/* Inclusion-exclusion (the third counting approach of Sec. 2)         */
+/* ------------------------------------------------------------------ */
+/*
+ * The universe is every placement of the n pairs inside the position set
+ * with overlaps allowed; A_i holds the placements that leave position i
+ * empty.  A placement is a pairing exactly when it leaves no position empty,
+ * so by inclusion-exclusion over the sets S of positions forced empty,
+ *
+ *     C(n) = sum_{S subset of P} (-1)^|S| prod_k N_k(P \ S),
+ *
+ * N_k(T) = number of a with a, a + d_k both in T.  orc_larsen_partial sums
+ * the terms whose S agrees with a fixed part (fixed_mask: positions decided;
+ * fixed_empty: those of them in S), each term from scratch, modulo p.
+ */
+typedef struct {
+    int m, n, top;
+    const int *pos, *d;
+    uint64_t set, fixed_mask, fixed_empty, p;
+    int freep[64], nf;
+    int split_bits;
+    int next;
+    pthread_mutex_t lock;
+    uint64_t acc;
+} ie_job;
+
+/* sum over the free positions' subsets with the top split_bits free
+ * positions set by hi, modulo p */
+static uint64_t ie_range(const ie_job *J, uint64_t hi)
+{
+    const int nlow = J->nf - J->split_bits;
+    uint64_t acc = 0;
+    for (uint64_t lo = 0; lo < (1ull << nlow); lo++) {
+        uint64_t empty = J->fixed_empty & J->fixed_mask;
+        uint64_t bits = lo | (hi << nlow);
+        for (int i = 0; i < J->nf; i++)
+            if ((bits >> i) & 1) empty |= 1ull << (J->freep[i] - 1);
+        const uint64_t T = J->set & ~empty;
+        u128 prod = 1;
+        for (int k = 0; k < J->n; k++) {
+            uint64_t c = 0;
+            for (int a = 1; a + J->d[k] <= J->top; a++)
+                if (((T >> (a - 1)) & 1) && ((T >> (a + J->d[k] - 1)) & 1)) c++;
+            prod = (prod * c) % J->p;
+        }
+        if (__builtin_popcountll(empty & J->set) & 1)
+            acc = (uint64_t)(((u128)acc + J->p - (uint64_t)prod) % J->p);
+        else
+            acc = (uint64_t)(((u128)acc + (uint64_t)prod) % J->p);
+    }
+    return acc;
+}
+
+static void *ie_worker(void *arg)
+{
+    ie_job *J = (ie_job *)arg;
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        int i = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (i >= (1 << J->split_bits)) break;
+        uint64_t r = ie_range(J, (uint64_t)i);
+        pthread_mutex_lock(&J->lock);
+        J->acc = (uint64_t)(((u128)J->acc + r) % J->p);
+        pthread_mutex_unlock(&J->lock);
+    }
+    return NULL;
+}
+
+uint64_t orc_larsen_partial(int n, int variant, uint64_t fixed_mask, uint64_t fixed_empty, uint64_t p,
+                            int threads)
+{
+    int pos[64], d[64];
+    int m = orc_instance(n, variant, pos, d);
+    if (m < 0 || p < 3) return 0;
+    ie_job J;
+    memset(&J, 0, sizeof(J));
+    J.m = m; J.n = n; J.top = pos[m - 1]; J.pos = pos; J.d = d;
+    J.set = position_mask(pos, m);
+    J.fixed_mask = fixed_mask & J.set;
+    J.fixed_empty = fixed_empty;
+    J.p = p;
+    for (int i = 0; i < m; i++)
+        if (!((J.fixed_mask >> (pos[i] - 1)) & 1)) J.freep[J.nf++] = pos[i];
+    int sb = 0;
+    if (threads > 1)
+        while ((1 << sb) < 4 * threads && sb < 8) sb++;
+    if (sb > J.nf) sb = J.nf;
+    J.split_bits = sb;
+    pthread_mutex_init(&J.lock, NULL);
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    pthread_t th[256];
+    for (int t = 0; t < threads; t++) pthread_create(&th[t], NULL, ie_worker, &J);
+    for (int t = 0; t < threads; t++) pthread_join(th[t], NULL);
+    pthread_mutex_destroy(&J.lock);
+    return J.acc;
+}

@@ -237,3 +237,54 @@ def test_primes():
     ps = O.primes_below(1 << 20, 5)
     assert all(O.is_prime(x) for x in ps) and len(set(ps)) == 5
     assert all(not O.is_prime(x) for x in range(ps[0] + 1, 1 << 20))
+
+
+# ---------------------------------------------------------------- Sec. 2, inclusion-exclusion
+
+def test_larsen_hand_computed_small_cases():
+    """n = 1: only S = {} contributes (one placement).  n = 2 Skolem on
+    positions 1..4, d = 1, 2: S = {} gives 3 * 2 = 6; S = {1}, {2}, {3}, {4}
+    give 2*1, 1*1, 1*1, 2*1; no two positions host both pairs: 6 - 6 = 0.
+    n = 4 Skolem: the worked example's 6 ordered pairings (Sec. 2.1)."""
+    assert O.larsen_literal(1, "skolem") == 1
+    assert O.larsen_literal(2, "skolem") == 0
+    assert O.larsen_literal(4, "skolem") == 6
+    assert O.larsen_literal(3, "langford") == 2
+
+
+@pytest.mark.parametrize("variant", ["skolem", "langford", "hooked"])
+def test_larsen_literal_equals_backtrack(variant):
+    for n in range(1, 8):
+        assert O.larsen_literal(n, variant) == O.count_backtrack(n, variant), (variant, n)
+
+
+@pytest.mark.parametrize("variant", ["skolem", "langford", "hooked"])
+def test_larsen_modular_equals_backtrack(variant):
+    p = O.primes_below(1 << 46, 1)[0]
+    for n in range(1, 12):
+        assert O.larsen_count(n, variant, p, threads=8) == O.count_backtrack(n, variant, threads=8), (variant, n)
+        if n <= 7:
+            assert O.larsen_count(n, variant, p) == O.larsen_literal(n, variant) % p
+
+
+def test_larsen_printed_s12_and_partials_add_up():
+    """S(12) = 227968 (Table 7), ordered 455936; splitting on any position
+    (occupied or forced empty) splits the sum."""
+    p = O.primes_below(1 << 46, 1)[0]
+    assert O.larsen_count(12, "skolem", p, threads=8) == 2 * 227968
+    for q in (1, 7, 18):
+        a = O.larsen_partial(9, "langford", {q: 0}, p)
+        b = O.larsen_partial(9, "langford", {q: 1}, p)
+        assert (a + b) % p == O.count_backtrack(9, "langford") % p
+    # a restriction of the C sum equals the same restriction of the literal
+    # Python sum (position 1 forced empty)
+    pos, d = O.instance(5, "skolem")
+    want = 0
+    for bits in range(1 << 9):
+        S = {pos[1 + i] for i in range(9) if (bits >> i) & 1} | {pos[0]}
+        T = [a for a in pos if a not in S]
+        prod = 1
+        for dk in d:
+            prod *= sum(1 for a in T if a + dk in T)
+        want += -prod if len(S) % 2 else prod
+    assert O.larsen_partial(5, "skolem", {1: 0}, p) == want % p
