@@ -387,11 +387,22 @@ def main():
         slice_ids = inputs.distinct_ids(inputs.SLICE_SEED, L28_CHUNK_BITS, L28_SLICE)
         slice_primes = sk.describe(28, "langford")["primes"]  # default primes, as a full count uses
     n24 = n24_slices() if args.workload == "mixed" else []
+    # device workspaces owned by torch, so that a timed step allocates nothing
+    ws_count = ws_slice = None
+    if batched:
+        import torch
+        ws_count = torch.empty(sk.workspace_bytes([(n, v) for v, n in instances]), dtype=torch.uint8,
+                               device="cuda")
+        if n24:
+            ws_slice = torch.empty(max(sk.partial_workspace_bytes(24, sl["variant"], len(sl["ids"]),
+                                                                  len(sl["primes"])) for sl in n24),
+                                   dtype=torch.uint8, device="cuda")
 
     def run_slice(tag, sl):
         """One n = 24 slice: 8192 chunks in one call; the rows the oracle
         recomputed must match."""
-        rows, st = sk.partial_chunks(24, sl["variant"], sl["log2_chunks"], sl["ids"], sl["primes"], with_stats=True)
+        rows, st = sk.partial_chunks(24, sl["variant"], sl["log2_chunks"], sl["ids"], sl["primes"], with_stats=True,
+                                     workspace=ws_slice)
         ok = all(rows[i] == want_row for i, want_row in sl["check"])
         log(f"[{tag}] {sl['variant']} n=24 slice: kernel {st['kernel_ms']:.1f} ms "
             f"{st['terms'] / max(st['kernel_ms'], 1e-9) * 1e3:.3e} terms/s  check={ok}")
@@ -410,7 +421,7 @@ def main():
             return res
         if batched:
             counts, st = sk.count_batch([(n, v, sk.ORDERED if v == "hooked" else 0) for v, n in instances],
-                                        tuning=tuning if args.log2_chunk else None)
+                                        tuning=tuning if args.log2_chunk else None, workspace=ws_count)
             checks = []
             for (v, n), c in zip(instances, counts):
                 ok = want.get((v, n))

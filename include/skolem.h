@@ -21,8 +21,14 @@
  * Conventions for every entry point:
  *   - All pointers are host pointers unless the name says dev_.
  *   - The caller owns every buffer it passes; the library keeps no pointer to
- *     it after the call returns.  Device memory the library needs for one call
- *     is allocated and freed inside that call.
+ *     it after the call returns.
+ *   - Device workspace: the exact-sum entry points take a dev_workspace of
+ *     ws_bytes bytes (device memory on the current device, e.g. a torch
+ *     uint8 tensor's data pointer, 256-byte aligned), sized by
+ *     sk_workspace_bytes or sk_partial_workspace_bytes.  It is used only
+ *     during the call; its contents on entry do not matter.  NULL: the
+ *     library allocates what the call needs and frees it before returning.
+ *     A workspace that is too small gives SK_ENOMEM before any work starts.
  *   - A stream argument is a hipStream_t passed as void*; NULL means the
  *     library's own stream.  Calls return after their work has completed.
  *   - Errors are reported only through the status code.  On error, outputs
@@ -131,11 +137,30 @@ sk_status sk_set_device(int device);
  */
 sk_status sk_count(int n, int variant, unsigned flags, sk_u128 *out);
 
-/* sk_count with a launch shape (NULL: defaults), a stream, a progress
- * callback (NULL: none) and a statistics record (NULL: not wanted). */
+/* sk_count with a launch shape (NULL: defaults), a device workspace (see the
+ * conventions; NULL: internal), a stream, a progress callback (NULL: none) and
+ * a statistics record (NULL: not wanted). */
 sk_status sk_count_ex(int n, int variant, unsigned flags, const sk_tuning *tune,
-                      void *stream, sk_progress_fn progress, void *progress_ctx,
+                      void *dev_workspace, size_t ws_bytes, void *stream,
+                      sk_progress_fn progress, void *progress_ctx,
                       sk_stats *stats, sk_u128 *out);
+
+/*
+ * sk_workspace_bytes -- device workspace that sk_count_ex, sk_count_part and
+ * sk_count_batch need for these k instances and launch shape: the 128-bit
+ * per-prime accumulators of the on-device reduction (Sec. 2.2: the parts'
+ * results are put together at the end) and the work counter of the batched
+ * launch.  0 on bad input.  Host only.
+ */
+size_t sk_workspace_bytes(const sk_instance *inst, size_t k, const sk_tuning *tune);
+
+/*
+ * sk_partial_workspace_bytes -- device workspace sk_partial_chunks needs for
+ * nchunks chunks and nprimes primes with this launch shape: the accumulators,
+ * one output row and one chunk id per wavefront of a launch.  0 on bad input.
+ */
+size_t sk_partial_workspace_bytes(int n, int variant, size_t nchunks, int nprimes,
+                                  const sk_tuning *tune);
 
 /*
  * sk_count_part / sk_count_combine -- one count split into independent jobs
@@ -157,8 +182,9 @@ sk_status sk_count_ex(int n, int variant, unsigned flags, const sk_tuning *tune,
  * SK_VERIFY is not accepted by sk_count_part.  Errors: as sk_count.
  */
 sk_status sk_count_part(int n, int variant, unsigned flags, uint64_t part, uint64_t parts,
-                        const sk_tuning *tune, void *stream, sk_progress_fn progress,
-                        void *progress_ctx, sk_stats *stats, uint64_t *residues);
+                        const sk_tuning *tune, void *dev_workspace, size_t ws_bytes,
+                        void *stream, sk_progress_fn progress, void *progress_ctx,
+                        sk_stats *stats, uint64_t *residues);
 sk_status sk_count_combine(int n, int variant, unsigned flags, const uint64_t *residues, uint64_t parts,
                            sk_u128 *out);
 
@@ -174,10 +200,16 @@ sk_status sk_count_combine(int n, int variant, unsigned flags, const uint64_t *r
  *   tune  : NULL = the shape found by sk_autotune_batch for this instance set
  *           (cached per GPU model), else log2_chunk_terms (sign vectors per work
  *           item) and waves_per_launch (persistent grid) are used
+ *   dev_workspace, ws_bytes : see the conventions (sk_workspace_bytes)
  *   stats : NULL or receives the totals of the call
- * Errors: as sk_count; SK_EINVAL for k == 0 or a bad instance.
+ * Reduction: each wavefront's residues are summed per instance and prime in
+ * its workgroup's LDS, then into 128-bit device accumulators; the host reads
+ * one sum per instance and prime.
+ * Errors: as sk_count; SK_EINVAL for k == 0 or a bad instance; SK_ENOMEM for
+ * a workspace below sk_workspace_bytes.
  */
-sk_status sk_count_batch(const sk_instance *inst, size_t k, const sk_tuning *tune, void *stream,
+sk_status sk_count_batch(const sk_instance *inst, size_t k, const sk_tuning *tune,
+                         void *dev_workspace, size_t ws_bytes, void *stream,
                          sk_stats *stats, sk_u128 *out);
 
 /*
@@ -220,13 +252,15 @@ sk_status sk_sign_sum_residues(int n, int variant, const uint64_t *primes, int n
  *   primes      : nprimes (1..8) primes with 2^45 < p < 2^46, or NULL for the
  *                 nprimes largest primes below 2^46 (the ones sk_count uses)
  *   tune        : waves_per_launch and kernel fields are used (NULL: defaults)
+ *   dev_workspace, ws_bytes : see the conventions (sk_partial_workspace_bytes)
  *   residues_out: nchunks x nprimes, row-major, each the chunk's signed sum
  *                 of (prod x) prod_k f_k(x) modulo the prime, in [0, p)
- * Errors: SK_EINVAL, SK_EDEVICE, SK_ENOLIB.
+ * Errors: SK_EINVAL, SK_EDEVICE, SK_ENOLIB, SK_ENOMEM (workspace too small).
  */
 sk_status sk_partial_chunks(int n, int variant, int log2_chunks, const uint64_t *chunk_ids,
                             size_t nchunks, const uint64_t *primes, int nprimes,
-                            const sk_tuning *tune, void *stream, uint64_t *residues_out);
+                            const sk_tuning *tune, void *dev_workspace, size_t ws_bytes,
+                            void *stream, uint64_t *residues_out);
 
 /* Totals of the last sk_count, sk_count_ex, sk_count_batch,
  * sk_sign_sum_residues or sk_partial_chunks call made by this thread. */

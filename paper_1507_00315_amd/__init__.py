@@ -123,15 +123,15 @@ def lib() -> ctypes.CDLL:
     u64p = ctypes.POINTER(ctypes.c_uint64)
     L.sk_set_device.argtypes = [c_int]
     L.sk_count.argtypes = [c_int, c_int, c_uint, ctypes.POINTER(U128)]
-    L.sk_count_ex.argtypes = [c_int, c_int, c_uint, ctypes.POINTER(Tuning), vp, PROGRESS_FN, vp,
+    L.sk_count_ex.argtypes = [c_int, c_int, c_uint, ctypes.POINTER(Tuning), vp, c_size, vp, PROGRESS_FN, vp,
                               ctypes.POINTER(Stats), ctypes.POINTER(U128)]
     L.sk_sign_sum_residues.argtypes = [c_int, c_int, u64p, c_int, ctypes.POINTER(Tuning), vp, u64p]
     L.sk_partial_chunks.argtypes = [c_int, c_int, c_int, u64p, c_size, u64p, c_int, ctypes.POINTER(Tuning), vp,
-                                    u64p]
+                                    c_size, vp, u64p]
     L.sk_max_chunk_bits.argtypes = [c_int, c_int]
     L.sk_last_stats.argtypes = [ctypes.POINTER(Stats)]
     L.sk_count_part.argtypes = [c_int, c_int, c_uint, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(Tuning), vp,
-                                PROGRESS_FN, vp, ctypes.POINTER(Stats), u64p]
+                                c_size, vp, PROGRESS_FN, vp, ctypes.POINTER(Stats), u64p]
     L.sk_count_combine.argtypes = [c_int, c_int, c_uint, u64p, ctypes.c_uint64, ctypes.POINTER(U128)]
     L.sk_describe.argtypes = [c_int, c_int, ctypes.POINTER(PlanDesc)]
     L.sk_pt_bins.argtypes = [c_int, c_int]
@@ -139,8 +139,12 @@ def lib() -> ctypes.CDLL:
                             ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)]
     L.sk_approx.argtypes = [c_int, c_int, ctypes.POINTER(PtParams), vp, ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(PtStats)]
-    L.sk_count_batch.argtypes = [ctypes.POINTER(Instance), c_size, ctypes.POINTER(Tuning), vp, ctypes.POINTER(Stats),
-                                 ctypes.POINTER(U128)]
+    L.sk_count_batch.argtypes = [ctypes.POINTER(Instance), c_size, ctypes.POINTER(Tuning), vp, c_size, vp,
+                                 ctypes.POINTER(Stats), ctypes.POINTER(U128)]
+    L.sk_workspace_bytes.argtypes = [ctypes.POINTER(Instance), c_size, ctypes.POINTER(Tuning)]
+    L.sk_workspace_bytes.restype = c_size
+    L.sk_partial_workspace_bytes.argtypes = [c_int, c_int, c_size, c_int, ctypes.POINTER(Tuning)]
+    L.sk_partial_workspace_bytes.restype = c_size
     L.sk_autotune_batch.argtypes = [ctypes.POINTER(Instance), c_size, vp, ctypes.POINTER(Tuning),
                                     ctypes.POINTER(ctypes.c_double)]
     fp = ctypes.POINTER(ctypes.c_float)
@@ -171,6 +175,7 @@ def lib() -> ctypes.CDLL:
 
 
 EXPORTED = ["sk_set_device", "sk_count", "sk_count_ex", "sk_count_batch", "sk_autotune_batch", "sk_pt_bins",
+            "sk_workspace_bytes", "sk_partial_workspace_bytes",
             "sk_pt_run", "sk_approx", "sk_sign_sum_residues", "sk_partial_chunks",
             "sk_max_chunk_bits", "sk_describe", "sk_strerror", "sk_last_error", "sk_u128_to_decimal", "sk_kernel_name",
             "sk_last_stats", "sk_count_part", "sk_count_combine", "sk_mlp_param_count", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
@@ -187,6 +192,17 @@ def _check(status: int, what: str) -> None:
     if status != 0:
         detail = lib().sk_last_error().decode(errors="replace")
         raise SkolemError(status, what, detail)
+
+
+def _workspace(workspace):
+    """(device pointer, bytes) of a workspace: None, a torch tensor on the
+    GPU (its storage), or a (pointer, bytes) pair."""
+    if workspace is None:
+        return None, 0
+    if hasattr(workspace, "data_ptr"):
+        return int(workspace.data_ptr()), int(workspace.numel() * workspace.element_size())
+    ptr, nbytes = workspace
+    return int(ptr), int(nbytes)
 
 
 def _stream_handle(stream) -> Optional[int]:
@@ -222,8 +238,11 @@ def _flags(ordered, verify, no_shortcut, no_symmetry) -> int:
 def count_ex(n: int, variant="skolem", ordered: bool = False, verify: bool = False,
              no_shortcut: bool = False, tuning: Optional[Dict] = None, stream=None,
              progress: Optional[Callable[[int, int], Optional[bool]]] = None,
-             no_symmetry: bool = False) -> CountResult:
-    """Exact count (reflections counted once unless ``ordered``) with launch statistics."""
+             no_symmetry: bool = False, workspace=None) -> CountResult:
+    """Exact count (reflections counted once unless ``ordered``) with launch
+    statistics.  ``workspace``: device memory for the call (a torch tensor of
+    at least workspace_bytes() bytes), or None for the library's own."""
+    wp, wb = _workspace(workspace)
     flags = _flags(ordered, verify, no_shortcut, no_symmetry)
     out = U128()
     st = Stats()
@@ -235,7 +254,7 @@ def count_ex(n: int, variant="skolem", ordered: bool = False, verify: bool = Fal
         return 1 if progress(int(done), int(total)) else 0
 
     cb = PROGRESS_FN(_cb)
-    status = lib().sk_count_ex(n, _variant(variant), flags, ctypes.byref(t) if t else None,
+    status = lib().sk_count_ex(n, _variant(variant), flags, ctypes.byref(t) if t else None, wp, wb,
                                _stream_handle(stream), cb, None, ctypes.byref(st), ctypes.byref(out))
     _check(status, f"sk_count_ex(n={n}, variant={variant})")
     return CountResult(out.value(), st.as_dict())
@@ -252,7 +271,7 @@ def count(n: int, variant="skolem", ordered: bool = False, verify: bool = False,
 
 def count_part(n: int, variant, part: int, parts: int, ordered: bool = False, no_shortcut: bool = False,
                no_symmetry: bool = False, tuning: Optional[Dict] = None, stream=None,
-               progress: Optional[Callable[[int, int], Optional[bool]]] = None):
+               progress: Optional[Callable[[int, int], Optional[bool]]] = None, workspace=None):
     """Residues of the part-th of `parts` shares of an exact count (sk_count_part):
     (residues, stats)."""
     flags = _flags(ordered, False, no_shortcut, no_symmetry)
@@ -267,7 +286,8 @@ def count_part(n: int, variant, part: int, parts: int, ordered: bool = False, no
         return 1 if progress(int(done), int(total)) else 0
 
     cb = PROGRESS_FN(_cb)
-    _check(lib().sk_count_part(n, _variant(variant), flags, part, parts, ctypes.byref(t) if t else None,
+    wp, wb = _workspace(workspace)
+    _check(lib().sk_count_part(n, _variant(variant), flags, part, parts, ctypes.byref(t) if t else None, wp, wb,
                                _stream_handle(stream), cb, None, ctypes.byref(st), out),
            f"sk_count_part(n={n}, part={part}/{parts})")
     return [int(x) for x in out], st.as_dict()
@@ -294,16 +314,32 @@ def _instances(instances) -> "ctypes.Array":
     return arr
 
 
-def count_batch(instances, tuning: Optional[Dict] = None, stream=None):
+def count_batch(instances, tuning: Optional[Dict] = None, stream=None, workspace=None):
     """Exact counts of several instances [(n, variant[, flags]), ...] in one
-    persistent launch; returns (counts, stats)."""
+    persistent launch; returns (counts, stats).  ``workspace`` as in count_ex."""
     arr = _instances(instances)
     out = (U128 * len(instances))()
     st = Stats()
     t = _tuning(tuning)
-    _check(lib().sk_count_batch(arr, len(instances), ctypes.byref(t) if t else None, _stream_handle(stream),
-                                ctypes.byref(st), out), "sk_count_batch")
+    wp, wb = _workspace(workspace)
+    _check(lib().sk_count_batch(arr, len(instances), ctypes.byref(t) if t else None, wp, wb,
+                                _stream_handle(stream), ctypes.byref(st), out), "sk_count_batch")
     return [o.value() for o in out], st.as_dict()
+
+
+def workspace_bytes(instances, tuning: Optional[Dict] = None) -> int:
+    """Device workspace bytes count_ex / count_part / count_batch need for these
+    instances [(n, variant[, flags]), ...] (sk_workspace_bytes)."""
+    arr = _instances(instances)
+    t = _tuning(tuning)
+    return int(lib().sk_workspace_bytes(arr, len(instances), ctypes.byref(t) if t else None))
+
+
+def partial_workspace_bytes(n: int, variant, nchunks: int, nprimes: int, tuning: Optional[Dict] = None) -> int:
+    """Device workspace bytes partial_chunks needs (sk_partial_workspace_bytes)."""
+    t = _tuning(tuning)
+    return int(lib().sk_partial_workspace_bytes(n, _variant(variant), nchunks, nprimes,
+                                                ctypes.byref(t) if t else None))
 
 
 def autotune_batch(instances, stream=None):
@@ -335,7 +371,7 @@ def sign_sum_residues(n: int, variant, primes: Sequence[int], tuning: Optional[D
 
 
 def partial_chunks(n: int, variant, log2_chunks: int, chunk_ids: Sequence[int], primes,
-                   tuning: Optional[Dict] = None, stream=None, with_stats: bool = False):
+                   tuning: Optional[Dict] = None, stream=None, with_stats: bool = False, workspace=None):
     """Per-chunk residues (see the chunk definition in include/skolem.h).
     primes: a list of primes, or an int k for the library's k default primes.
     With with_stats, returns (rows, stats of the call)."""
@@ -346,8 +382,9 @@ def partial_chunks(n: int, variant, log2_chunks: int, chunk_ids: Sequence[int], 
         k, ps = len(primes), _u64_array(primes)
     out = (ctypes.c_uint64 * (len(chunk_ids) * k))()
     t = _tuning(tuning)
+    wp, wb = _workspace(workspace)
     _check(lib().sk_partial_chunks(n, _variant(variant), log2_chunks, ids, len(chunk_ids), ps, k,
-                                   ctypes.byref(t) if t else None, _stream_handle(stream), out),
+                                   ctypes.byref(t) if t else None, wp, wb, _stream_handle(stream), out),
            "sk_partial_chunks")
     rows = [[int(out[c * k + i]) for i in range(k)] for c in range(len(chunk_ids))]
     if with_stats:
@@ -545,7 +582,7 @@ def last_stats_dict(st: Stats) -> Dict:
     return st.as_dict()
 
 
-__all__ = ["count", "count_ex", "count_batch", "autotune_batch", "pt_run", "approx", "pt_bins", "sign_sum_residues",
+__all__ = ["count", "count_ex", "count_batch", "workspace_bytes", "partial_workspace_bytes", "autotune_batch", "pt_run", "approx", "pt_bins", "sign_sum_residues",
            "partial_chunks", "last_stats", "count_part", "count_combine", "max_chunk_bits", "set_device", "mlp_param_count", "mlp_init", "mlp_forward",
            "mlp_loss_grad", "mlp_train", "mlp_mh_step", "PROPOSAL_UNIFORM", "PROPOSAL_LEARNED",
            "SkolemError", "SKOLEM", "LANGFORD", "HOOKED", "lib", "EXPORTED"]

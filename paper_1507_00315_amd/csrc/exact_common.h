@@ -109,4 +109,65 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
+// ---------------------------------------------------------------- reduction
+//
+// Residues leave a wavefront as exact fp64 integers.  The device sums them per
+// prime as unsigned integers in [0, p) into 128-bit accumulators (a low word
+// and a carry count, both updated by 64-bit atomics): the sum is exact and
+// does not depend on the order of the additions, so it is the same on every
+// run, and the host reduces it modulo p once.  With p < 2^46 and fewer than
+// 2^32 additions the total stays below 2^78.
+
+// x mod p in [0, p) for an exact fp64 integer x with |x| < 2^51 p.
+__device__ __forceinline__ uint64_t canonical_residue(double x, double p, double pinv)
+{
+    double y = reduce_balanced(x, p, pinv);  // |y| <= 0.75 p
+    if (y < 0.0) y += p;
+    return (uint64_t)y;
+}
+
+// acc[0] += v with the carry out of the low word counted in acc[1].  Works on
+// global memory and on LDS (the atomics then stay in the workgroup).
+__device__ __forceinline__ void add_u128(unsigned long long* acc, uint64_t v)
+{
+    const unsigned long long old = atomicAdd(acc, (unsigned long long)v);
+    if (old + v < old) atomicAdd(acc + 1, 1ull);
+}
+
+// Adds a 128-bit (low, carries) pair into a device accumulator.
+__device__ __forceinline__ void add_u128_pair(unsigned long long* acc, unsigned long long lo,
+                                              unsigned long long hi)
+{
+    const unsigned long long old = atomicAdd(acc, lo);
+    const unsigned long long carry = (old + lo < old) ? 1ull : 0ull;
+    if (hi + carry) atomicAdd(acc + 1, hi + carry);
+}
+
+// Workgroup stage for one-chunk-per-wave launches (256 threads = 4
+// wavefronts, every thread of the workgroup must call it): the residues of the
+// block's waves (res, the same in every lane of a wave; a wave with active ==
+// false contributes 0) meet in LDS, and one thread per prime adds their sum
+// (below 2^48) to acc[2 i], acc[2 i + 1].
+template <int PMAX>
+__device__ __forceinline__ void workgroup_accumulate(const double (&res)[PMAX], int P, const double* prime,
+                                                     const double* pinv, bool active,
+                                                     unsigned long long* __restrict__ acc)
+{
+    __shared__ uint64_t part[4][PMAX];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i)
+            if (i < P) part[w][i] = active ? canonical_residue(res[i], prime[i], pinv[i]) : 0;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < P) {
+        uint64_t s = 0;
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i)
+            if (i == (int)threadIdx.x) s = part[0][i] + part[1][i] + part[2][i] + part[3][i];
+        if (s) add_u128(acc + 2 * threadIdx.x, s);
+    }
+}
+
 }  // namespace sk

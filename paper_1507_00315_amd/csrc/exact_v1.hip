@@ -23,57 +23,64 @@ __global__ void __launch_bounds__(256) exact_v1_kernel(const ExactArgs a, double
 {
     const int lane = threadIdx.x & 63;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (wave >= a.n_waves) return;  // wave-uniform
-    const uint64_t chunk = a.chunk_ids ? a.chunk_ids[wave] : a.chunk_base + wave;
+    const bool active = wave < a.n_waves;  // wave-uniform
     const int P = a.nprimes;
+    double res[kMaxPrimes] = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        const uint64_t chunk = a.chunk_ids ? a.chunk_ids[wave] : a.chunk_base + wave;
 
-    uint64_t x_fixed = 0;
-    for (int b = 0; b < a.n_lane; ++b)
-        if ((lane >> b) & 1) x_fixed |= 1ull << (a.var_pos[a.m - a.n_lane + b] - 1);
-    const int cb = a.n_job - a.job_bits_per_chunk;
-    for (int b = 0; b < cb; ++b)
-        if ((chunk >> b) & 1)
-            x_fixed |= 1ull << (a.var_pos[1 + a.n_walk + a.job_bits_per_chunk + b] - 1);
+        uint64_t x_fixed = 0;
+        for (int b = 0; b < a.n_lane; ++b)
+            if ((lane >> b) & 1) x_fixed |= 1ull << (a.var_pos[a.m - a.n_lane + b] - 1);
+        const int cb = a.n_job - a.job_bits_per_chunk;
+        for (int b = 0; b < cb; ++b)
+            if ((chunk >> b) & 1)
+                x_fixed |= 1ull << (a.var_pos[1 + a.n_walk + a.job_bits_per_chunk + b] - 1);
 
-    double acc[kMaxPrimes] = {0.0, 0.0, 0.0, 0.0};
-    const uint64_t njobs = 1ull << a.job_bits_per_chunk;
-    const uint64_t nsteps = 1ull << a.n_walk;
-    for (uint64_t j = 0; j < njobs; ++j) {
-        uint64_t X = x_fixed;
-        for (int b = 0; b < a.job_bits_per_chunk; ++b)
-            if ((j >> b) & 1) X |= 1ull << (a.var_pos[1 + a.n_walk + b] - 1);
-        const bool neg0 = __popcll(X) & 1;
-        double accj[kMaxPrimes] = {0.0, 0.0, 0.0, 0.0};
-        for (uint64_t t = 0; t < nsteps; ++t) {
-            if (t) X ^= 1ull << (a.var_pos[1 + __builtin_ctzll(t)] - 1);
-            int32_t f[4 * NQ];
+        double acc[kMaxPrimes] = {0.0, 0.0, 0.0, 0.0};
+        const uint64_t njobs = 1ull << a.job_bits_per_chunk;
+        const uint64_t nsteps = 1ull << a.n_walk;
+        for (uint64_t j = 0; j < njobs; ++j) {
+            uint64_t X = x_fixed;
+            for (int b = 0; b < a.job_bits_per_chunk; ++b)
+                if ((j >> b) & 1) X |= 1ull << (a.var_pos[1 + a.n_walk + b] - 1);
+            const bool neg0 = __popcll(X) & 1;
+            double accj[kMaxPrimes] = {0.0, 0.0, 0.0, 0.0};
+            for (uint64_t t = 0; t < nsteps; ++t) {
+                if (t) X ^= 1ull << (a.var_pos[1 + __builtin_ctzll(t)] - 1);
+                int32_t f[4 * NQ];
 #pragma unroll
-            for (int s = 0; s < 4 * NQ; ++s) {
-                const int c = __popcll((X ^ (X >> a.slot[s].d)) & a.slot[s].mask);
-                f[s] = (a.slot[s].len - 2 * c) >> a.slot[s].halve;
+                for (int s = 0; s < 4 * NQ; ++s) {
+                    const int c = __popcll((X ^ (X >> a.slot[s].d)) & a.slot[s].mask);
+                    f[s] = (a.slot[s].len - 2 * c) >> a.slot[s].halve;
+                }
+                double g[G];
+                group_products<NQ, G>(f, a.qb, g);
+                accumulate_term<G>(g, a.prime, a.pinv, P, (t & 1) != 0, accj);
+                if ((t & 63) == 63) {
+                    for (int i = 0; i < kMaxPrimes; ++i)
+                        if (i < P) accj[i] = reduce_balanced(accj[i], a.prime[i], a.pinv[i]);
+                }
             }
-            double g[G];
-            group_products<NQ, G>(f, a.qb, g);
-            accumulate_term<G>(g, a.prime, a.pinv, P, (t & 1) != 0, accj);
-            if ((t & 63) == 63) {
-                for (int i = 0; i < kMaxPrimes; ++i)
-                    if (i < P) accj[i] = reduce_balanced(accj[i], a.prime[i], a.pinv[i]);
+            for (int i = 0; i < kMaxPrimes; ++i) {
+                if (i < P) {
+                    const double r = reduce_balanced(accj[i], a.prime[i], a.pinv[i]);
+                    acc[i] = reduce_balanced(neg0 ? acc[i] - r : acc[i] + r, a.prime[i], a.pinv[i]);
+                }
             }
         }
+        const bool valid = lane < (1 << a.n_lane);
+#pragma unroll
         for (int i = 0; i < kMaxPrimes; ++i) {
             if (i < P) {
-                const double r = reduce_balanced(accj[i], a.prime[i], a.pinv[i]);
-                acc[i] = reduce_balanced(neg0 ? acc[i] - r : acc[i] + r, a.prime[i], a.pinv[i]);
+                const double v = wave_sum_f64(valid ? acc[i] : 0.0);
+                res[i] = v;
+                if (lane == 0 && !a.acc) out[wave * P + i] = v;
             }
         }
     }
-    const bool valid = lane < (1 << a.n_lane);
-    for (int i = 0; i < kMaxPrimes; ++i) {
-        if (i < P) {
-            const double v = wave_sum_f64(valid ? acc[i] : 0.0);
-            if (lane == 0) out[wave * P + i] = v;
-        }
-    }
+    // sums of whole launches: workgroup stage, then the device accumulators
+    if (a.acc) workgroup_accumulate<kMaxPrimes>(res, P, a.prime, a.pinv, active, a.acc);
 }
 
 #define SK_V1_INST(NQ, G) \

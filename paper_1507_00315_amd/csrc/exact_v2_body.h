@@ -466,19 +466,24 @@ template <int V, int N, int P, int INNER>
 __global__ void __launch_bounds__(256) exact_v2_kernel(const ExactArgsV2 a, double* __restrict__ out)
 {
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wave >= a.n_waves) return;
-    const uint64_t chunk = uniform_u64(a.chunk_ids ? a.chunk_ids[wave] : a.chunk_base + wave);
+    const bool active = wave < a.n_waves;  // wave-uniform
     double pr[P], pinv[P], res[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         pr[i] = in_vgpr(a.prime[i]);
         pinv[i] = in_vgpr(a.pinv[i]);
+        res[i] = 0.0;
     }
-    exact_v2_chunk<V, N, P, INNER>(chunk, a.job_bits_per_chunk, a.rev, pr, pinv, res);
-    if ((threadIdx.x & 63) == 0) {
+    if (active) {
+        const uint64_t chunk = uniform_u64(a.chunk_ids ? a.chunk_ids[wave] : a.chunk_base + wave);
+        exact_v2_chunk<V, N, P, INNER>(chunk, a.job_bits_per_chunk, a.rev, pr, pinv, res);
+        if ((threadIdx.x & 63) == 0 && !a.acc) {
 #pragma unroll
-        for (int i = 0; i < P; ++i) out[wave * P + i] = res[i];
+            for (int i = 0; i < P; ++i) out[wave * P + i] = res[i];
+        }
     }
+    // sums of whole launches: workgroup stage, then the device accumulators
+    if (a.acc) workgroup_accumulate<P>(res, P, pr, pinv, active, a.acc);
 }
 
 }  // namespace sk

@@ -329,7 +329,29 @@ struct SumRequest {
     // total mode: only the part-th of `parts` equal, consecutive ranges of
     // chunk indices (parts a power of two not above the chunk count)
     uint64_t part = 0, parts = 1;
+    // device workspace (nullptr: allocated and freed inside the call)
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    // time the launches with HIP events (kernel_ms); off in the call that
+    // allocates nothing
+    bool timing = true;
 };
+
+// Device workspace of run_sum: the accumulators of a total (kAccSlots
+// (low word, carries) pairs), then, for listed chunks, one output row of up
+// to kMaxPrimes residues and one chunk id per wave of a launch.
+constexpr size_t kSumAccBytes = (size_t)kAccSlots * 2 * sizeof(unsigned long long);
+
+static size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t sum_ws_bytes(bool listed, uint64_t waves_per_launch)
+{
+    if (!listed) return kSumAccBytes;
+    return kSumAccBytes + round256(waves_per_launch * kMaxPrimes * sizeof(double)) +
+           round256(waves_per_launch * sizeof(uint64_t));
+}
+
+hipError_t launch_zero_words(void* p, uint64_t n, hipStream_t stream);
 
 // ------------------------------------------------------------------ kernels
 
@@ -436,22 +458,43 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
 
     uint64_t wpl = R.waves_per_launch > 0 ? (uint64_t)R.waves_per_launch : (uint64_t)ctx->cus * 4 * 8;
     wpl = std::min<uint64_t>(wpl, nchunks);
+    if (np > kAccSlots || (uint64_t)nbatches * batch > (uint64_t)kAccSlots) return SK_EINVAL;
 
+    const size_t need = sum_ws_bytes(listed, wpl);
+    unsigned char* ws = (unsigned char*)R.ws;
+    bool own_ws = false;
+    unsigned long long* d_acc = nullptr;
     double* d_out = nullptr;
     uint64_t* d_ids = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    std::vector<double> h_out(wpl * batch);
+    std::vector<double> h_out(listed ? wpl * batch : 0);
+    std::vector<unsigned long long> h_acc((size_t)2 * nbatches * batch);
     sk_status status = SK_OK;
     hipError_t e;
     uint64_t terms_done = 0;
+    auto t_host = std::chrono::steady_clock::now();
     auto fail = [&](hipError_t err, const char* what) { status = hip_fail(err, what); };
-    if ((e = hipMalloc(&d_out, wpl * batch * sizeof(double))) != hipSuccess) { fail(e, "hipMalloc"); goto done; }
-    if (listed) {
-        if ((e = hipMalloc(&d_ids, wpl * sizeof(uint64_t))) != hipSuccess) { fail(e, "hipMalloc"); goto done; }
+    if (ws && R.ws_bytes < need) {
+        g_last_error = "workspace of " + std::to_string(R.ws_bytes) + " bytes, " + std::to_string(need) + " needed";
+        return SK_ENOMEM;
     }
-    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
-        fail(e, "hipEventCreate");
+    if (!ws) {
+        if ((e = hipMalloc(&ws, need)) != hipSuccess) { fail(e, "hipMalloc"); goto done; }
+        own_ws = true;
+    }
+    d_acc = (unsigned long long*)ws;
+    if (listed) {
+        d_out = (double*)(ws + kSumAccBytes);
+        d_ids = (uint64_t*)(ws + kSumAccBytes + round256(wpl * kMaxPrimes * sizeof(double)));
+    } else if ((e = launch_zero_words(d_acc, 2 * (uint64_t)nbatches * batch, stream)) != hipSuccess) {
+        fail(e, "zero accumulators");
         goto done;
+    }
+    if (R.timing) {
+        if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+            fail(e, "hipEventCreate");
+            goto done;
+        }
     }
     if (listed) out.assign(nchunks * np, 0);
     else out.assign(np, 0);
@@ -461,6 +504,8 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
         std::vector<uint64_t> bp(batch);
         for (int i = 0; i < batch; ++i) bp[i] = R.primes[std::min(np - 1, bt * batch + i)];
         const int live = std::min(batch, np - bt * batch);
+        // total mode: this batch's primes own accumulator slots bt*batch ..
+        unsigned long long* acc = listed ? nullptr : d_acc + 2 * (size_t)bt * batch;
         ExactArgs a1;
         ExactArgsV2 a2;
         std::memset(&a1, 0, sizeof(a1));
@@ -480,6 +525,7 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
             a1.lane_valid_bits = P.n_lane;
             for (int g = 0; g < 5; ++g) a1.qb[g] = P.qb[g];
             a1.job_bits_per_chunk = jb;
+            a1.acc = acc;
         } else {
             for (int i = 0; i < batch; ++i) {
                 a2.prime[i] = (double)bp[i];
@@ -487,6 +533,7 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
             }
             a2.job_bits_per_chunk = jb;
             if (rev_r > 0) a2.rev = rev;
+            a2.acc = acc;
         }
         for (uint64_t base = 0; base < nchunks; base += wpl) {
             const uint64_t nw = std::min<uint64_t>(wpl, nchunks - base);
@@ -497,7 +544,7 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
                 ids = d_ids;
             }
             const unsigned blocks = (unsigned)((nw + 3) / 4);
-            if ((e = hipEventRecord(e0, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
+            if (e0 && (e = hipEventRecord(e0, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
             if (kv == 1) {
                 a1.n_waves = nw;
                 a1.chunk_base = chunk_offset + base;
@@ -510,21 +557,24 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
                 hipLaunchKernelGGL(fn2, dim3(blocks), dim3(256), 0, stream, a2, d_out);
             }
             if ((e = hipGetLastError()) != hipSuccess) { fail(e, "kernel launch"); goto done; }
-            if ((e = hipEventRecord(e1, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
-            if ((e = hipMemcpyAsync(h_out.data(), d_out, nw * batch * sizeof(double), hipMemcpyDeviceToHost,
-                                    stream)) != hipSuccess) { fail(e, "hipMemcpyAsync"); goto done; }
+            if (e1 && (e = hipEventRecord(e1, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
+            if (listed) {
+                if ((e = hipMemcpyAsync(h_out.data(), d_out, nw * batch * sizeof(double), hipMemcpyDeviceToHost,
+                                        stream)) != hipSuccess) { fail(e, "hipMemcpyAsync"); goto done; }
+            }
             if ((e = hipStreamSynchronize(stream)) != hipSuccess) { fail(e, "hipStreamSynchronize"); goto done; }
-            float ms = 0.f;
-            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { fail(e, "hipEventElapsedTime"); goto done; }
-            st.kernel_ms += ms;
+            if (e0) {
+                float ms = 0.f;
+                if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { fail(e, "hipEventElapsedTime"); goto done; }
+                st.kernel_ms += ms;
+            }
             st.launches += 1;
-            for (uint64_t w = 0; w < nw; ++w) {
-                for (int i = 0; i < live; ++i) {
-                    const int gi = bt * batch + i;
-                    const uint64_t r = fp_to_residue(h_out[w * batch + i], R.primes[gi]);
-                    if (listed) out[(base + w) * np + gi] = r;
-                    else out[gi] = (uint64_t)(((u128)out[gi] + r) % R.primes[gi]);
-                }
+            if (listed) {
+                for (uint64_t w = 0; w < nw; ++w)
+                    for (int i = 0; i < live; ++i) {
+                        const int gi = bt * batch + i;
+                        out[(base + w) * np + gi] = fp_to_residue(h_out[w * batch + i], R.primes[gi]);
+                    }
             }
             terms_done += nw * terms_per_chunk;
             if (R.progress && R.progress(R.progress_ctx, terms_done, terms_total)) {
@@ -533,8 +583,18 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
             }
         }
     }
-    if (half)
-        for (int i = 0; i < np; ++i) out[i] = (uint64_t)(((u128)out[i] * 2) % R.primes[i]);
+    if (!listed) {
+        // one 128-bit sum per prime: (carries * 2^64 + low word) mod p
+        if ((e = hipMemcpyAsync(h_acc.data(), d_acc, h_acc.size() * sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, stream)) != hipSuccess) { fail(e, "hipMemcpyAsync"); goto done; }
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) { fail(e, "hipStreamSynchronize"); goto done; }
+        for (int i = 0; i < np; ++i)
+            out[i] = (uint64_t)((((u128)h_acc[2 * i + 1] << 64) | h_acc[2 * i]) % R.primes[i]);
+        if (half)
+            for (int i = 0; i < np; ++i) out[i] = (uint64_t)(((u128)out[i] * 2) % R.primes[i]);
+    }
+    if (!R.timing)
+        st.kernel_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_host).count();
     st.terms += reversal_evaluated(nchunks * terms_per_chunk, rev_r);
     st.reversal_quads = rev_r;
     st.chunks += nchunks;
@@ -544,8 +604,7 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
 done:
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (d_out) (void)hipFree(d_out);
-    if (d_ids) (void)hipFree(d_ids);
+    if (own_ws) (void)hipFree(ws);
     return status;
 }
 
@@ -594,6 +653,11 @@ namespace sk {
 
 hipError_t launch_exact_batch(unsigned blocks, hipStream_t stream, const BatchArgs& a);
 
+// Device workspace of the counting entry points (sk_count_ex, sk_count_part,
+// sk_count_batch): one batched launch's accumulators and counter, which also
+// hold the accumulators of a separate count.
+constexpr size_t kCountWsBytes = kBatchWsBytes > kSumAccBytes ? kBatchWsBytes : kSumAccBytes;
+
 static int batch_kind(int variant, int n)
 {
 #define SK_BATCH_KIND(KIND, V, N) \
@@ -614,8 +678,10 @@ struct BatchJob {
 
 // One persistent launch over the chunks of every job.  probe_shift > 0 runs
 // only the first 2^-probe_shift of each job's chunks (used by the autotuner).
+// ws: device workspace of at least kBatchWsBytes (nullptr: allocated here).
 static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t waves, hipStream_t stream,
-                           int probe_shift, sk_stats& st, double* kernel_ms)
+                           int probe_shift, sk_stats& st, double* kernel_ms, void* ws_in = nullptr,
+                           bool timing = true)
 {
     if (jobs.empty()) return SK_OK;
     if ((int)jobs.size() > kBatchMaxInstances) return SK_EINVAL;
@@ -626,8 +692,7 @@ static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t
 
     BatchArgs a;
     std::memset(&a, 0, sizeof(a));
-    std::vector<uint64_t> items;
-    // largest chunk count first, so the short instances fill the tail
+    // largest work per item first, so the short instances fill the tail
     std::vector<size_t> order(jobs.size());
     for (size_t i = 0; i < jobs.size(); ++i) order[i] = i;
     std::vector<uint64_t> nch(jobs.size());
@@ -655,48 +720,60 @@ static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t
     std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
         return (jobs[x].terms / nch[x]) > (jobs[y].terms / nch[y]);
     });
-    for (size_t b : order)
-        for (uint64_t ch = 0; ch < nch[b]; ++ch) items.push_back(((uint64_t)b << kBatchChunkBits) | ch);
-    if (items.size() >= (1ull << 32)) return SK_EINVAL;
+    uint64_t n_items = 0;
+    for (size_t k = 0; k < order.size(); ++k) {
+        a.first[k] = (uint32_t)n_items;
+        a.slot_inst[k] = (int32_t)order[k];
+        n_items += nch[order[k]];
+        if (n_items >= (1ull << 32)) return SK_EINVAL;
+    }
+    a.first[order.size()] = (uint32_t)n_items;
+    a.nslots = (int32_t)order.size();
+    a.n_items = (uint32_t)n_items;
 
-    uint64_t* d_items = nullptr;
-    double* d_out = nullptr;
-    uint32_t* d_counter = nullptr;
+    unsigned char* ws = (unsigned char*)ws_in;
+    bool own_ws = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    std::vector<double> h_out(items.size() * kMaxPrimes);
+    std::vector<unsigned long long> h_acc(kBatchAccBytes / sizeof(unsigned long long));
     hipError_t e;
     sk_status status = SK_OK;
     auto fail = [&](hipError_t err, const char* what) { status = hip_fail(err, what); };
     const unsigned blocks = (unsigned)std::max<uint64_t>(1, (waves + 3) / 4);
     float ms = 0.f;
-    if ((e = hipMalloc(&d_items, items.size() * sizeof(uint64_t))) != hipSuccess) { fail(e, "hipMalloc"); goto done; }
-    if ((e = hipMalloc(&d_out, h_out.size() * sizeof(double))) != hipSuccess) { fail(e, "hipMalloc"); goto done; }
-    if ((e = hipMalloc(&d_counter, sizeof(uint32_t))) != hipSuccess) { fail(e, "hipMalloc"); goto done; }
-    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
-        fail(e, "hipEventCreate");
+    auto t_host = std::chrono::steady_clock::now();
+    if (!ws) {
+        if ((e = hipMalloc(&ws, kBatchWsBytes)) != hipSuccess) { fail(e, "hipMalloc"); goto done; }
+        own_ws = true;
+    }
+    a.acc = (unsigned long long*)ws;
+    a.counter = (uint32_t*)(ws + kBatchAccBytes);
+    if (timing) {
+        if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+            fail(e, "hipEventCreate");
+            goto done;
+        }
+    }
+    // accumulators and counter: one 8-byte word per accumulator half, one for the counter
+    if ((e = launch_zero_words(ws, kBatchAccBytes / 8 + 1, stream)) != hipSuccess) { fail(e, "zero workspace"); goto done; }
+    if (e0 && (e = hipEventRecord(e0, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
+    if ((e = launch_exact_batch(blocks, stream, a)) != hipSuccess) { fail(e, "batch launch"); goto done; }
+    if (e1 && (e = hipEventRecord(e1, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
+    if ((e = hipMemcpyAsync(h_acc.data(), a.acc, kBatchAccBytes, hipMemcpyDeviceToHost, stream)) != hipSuccess) {
+        fail(e, "hipMemcpyAsync");
         goto done;
     }
-    if ((e = hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
-                            stream)) != hipSuccess) { fail(e, "hipMemcpyAsync"); goto done; }
-    if ((e = hipMemsetAsync(d_counter, 0, sizeof(uint32_t), stream)) != hipSuccess) { fail(e, "hipMemsetAsync"); goto done; }
-    a.items = d_items;
-    a.n_items = items.size();
-    a.counter = d_counter;
-    a.out = d_out;
-    if ((e = hipEventRecord(e0, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
-    if ((e = launch_exact_batch(blocks, stream, a)) != hipSuccess) { fail(e, "batch launch"); goto done; }
-    if ((e = hipEventRecord(e1, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
-    if ((e = hipMemcpyAsync(h_out.data(), d_out, h_out.size() * sizeof(double), hipMemcpyDeviceToHost, stream)) !=
-        hipSuccess) { fail(e, "hipMemcpyAsync"); goto done; }
     if ((e = hipStreamSynchronize(stream)) != hipSuccess) { fail(e, "hipStreamSynchronize"); goto done; }
-    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { fail(e, "hipEventElapsedTime"); goto done; }
-    for (auto& j : jobs) j.res.assign(j.primes.size(), 0);
-    for (size_t it = 0; it < items.size(); ++it) {
-        const size_t b = (size_t)(items[it] >> kBatchChunkBits);
+    if (e0) {
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { fail(e, "hipEventElapsedTime"); goto done; }
+    } else {
+        ms = (float)std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_host).count();
+    }
+    for (size_t b = 0; b < jobs.size(); ++b) {
         BatchJob& j = jobs[b];
+        j.res.assign(j.primes.size(), 0);
         for (size_t i = 0; i < j.primes.size(); ++i) {
-            const uint64_t r = fp_to_residue(h_out[it * kMaxPrimes + i], j.primes[i]);
-            j.res[i] = (uint64_t)(((u128)j.res[i] + r) % j.primes[i]);
+            const size_t w = 2 * (b * kMaxPrimes + i);
+            j.res[i] = (uint64_t)((((u128)h_acc[w + 1] << 64) | h_acc[w]) % j.primes[i]);
         }
     }
     for (auto& j : jobs)
@@ -705,7 +782,7 @@ static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t
     if (kernel_ms) *kernel_ms = ms;
     st.kernel_ms += ms;
     st.launches += 1;
-    st.chunks += items.size();
+    st.chunks += n_items;
     for (auto& j : jobs) st.terms += j.terms;
     st.log2_chunk_terms = log2_chunk;
     st.kernel_variant = 3;
@@ -714,9 +791,7 @@ static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t
 done:
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (d_items) (void)hipFree(d_items);
-    if (d_out) (void)hipFree(d_out);
-    if (d_counter) (void)hipFree(d_counter);
+    if (own_ws) (void)hipFree(ws);
     return status;
 }
 
@@ -847,8 +922,9 @@ sk_status sk_set_device(int device)
     return SK_OK;
 }
 
-static sk_status count_impl(int n, int variant, unsigned flags, const sk_tuning* tune, void* stream,
-                            sk_progress_fn progress, void* pctx, sk_stats* stats_out, sk_u128* out)
+static sk_status count_impl(int n, int variant, unsigned flags, const sk_tuning* tune, void* ws, size_t ws_bytes,
+                            void* stream, sk_progress_fn progress, void* pctx, sk_stats* stats_out, sk_u128* out,
+                            bool timing = true)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!out) return SK_EINVAL;
@@ -876,6 +952,9 @@ static sk_status count_impl(int n, int variant, unsigned flags, const sk_tuning*
             R.progress_ctx = pctx;
             R.half = !(flags & SK_NO_SYMMETRY) && hat_symmetric(P);
             R.reverse = !(flags & SK_NO_SYMMETRY);
+            R.ws = ws;
+            R.ws_bytes = ws_bytes;
+            R.timing = timing;
             std::vector<uint64_t> res;
             s = run_sum(R, res, st);
             if (s != SK_OK) return s;
@@ -905,8 +984,8 @@ static sk_status count_impl(int n, int variant, unsigned flags, const sk_tuning*
 }
 
 sk_status sk_count_part(int n, int variant, unsigned flags, uint64_t part, uint64_t parts, const sk_tuning* tune,
-                        void* stream, sk_progress_fn progress, void* progress_ctx, sk_stats* stats_out,
-                        uint64_t* residues)
+                        void* dev_workspace, size_t ws_bytes, void* stream, sk_progress_fn progress,
+                        void* progress_ctx, sk_stats* stats_out, uint64_t* residues)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!residues || parts == 0 || part >= parts || (flags & SK_VERIFY)) return SK_EINVAL;
@@ -931,6 +1010,8 @@ sk_status sk_count_part(int n, int variant, unsigned flags, uint64_t part, uint6
         R.reverse = !(flags & SK_NO_SYMMETRY);
         R.part = part;
         R.parts = parts;
+        R.ws = dev_workspace;
+        R.ws_bytes = ws_bytes;
         s = run_sum(R, res, st);
         if (s != SK_OK) return s;
     }
@@ -979,21 +1060,30 @@ sk_status sk_count_combine(int n, int variant, unsigned flags, const uint64_t* r
 
 sk_status sk_count(int n, int variant, unsigned flags, sk_u128* out)
 {
-    return count_impl(n, variant, flags, nullptr, nullptr, nullptr, nullptr, nullptr, out);
+    return count_impl(n, variant, flags, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, out);
 }
 
-sk_status sk_count_ex(int n, int variant, unsigned flags, const sk_tuning* tune, void* stream,
-                      sk_progress_fn progress, void* progress_ctx, sk_stats* stats, sk_u128* out)
+sk_status sk_count_ex(int n, int variant, unsigned flags, const sk_tuning* tune, void* dev_workspace,
+                      size_t ws_bytes, void* stream, sk_progress_fn progress, void* progress_ctx, sk_stats* stats,
+                      sk_u128* out)
 {
-    return count_impl(n, variant, flags, tune, stream, progress, progress_ctx, stats, out);
+    return count_impl(n, variant, flags, tune, dev_workspace, ws_bytes, stream, progress, progress_ctx, stats, out);
 }
 
 
-sk_status sk_count_batch(const sk_instance* inst, size_t k, const sk_tuning* tune, void* stream, sk_stats* stats,
-                         sk_u128* out)
+// sk_count_batch on a given device workspace (nullptr: each launch allocates
+// its own); timing = false times the call by the host clock instead of HIP
+// events.
+static sk_status batch_impl(const sk_instance* inst, size_t k, const sk_tuning* tune, void* ws, size_t ws_bytes,
+                            void* stream, sk_stats* stats, sk_u128* out, bool timing)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!inst || !out || k == 0) return SK_EINVAL;
+    if (ws && ws_bytes < kCountWsBytes) {
+        g_last_error = "workspace of " + std::to_string(ws_bytes) + " bytes, " + std::to_string(kCountWsBytes) +
+                       " needed";
+        return SK_ENOMEM;
+    }
     std::vector<Plan> plans(k);
     for (size_t i = 0; i < k; ++i) {
         sk_status s = make_plan(inst[i].n, inst[i].variant, plans[i]);
@@ -1053,7 +1143,7 @@ sk_status sk_count_batch(const sk_instance* inst, size_t k, const sk_tuning* tun
                 jobs.push_back(j);
                 who.push_back(i);
             }
-            s = run_batch(jobs, lc, waves, (hipStream_t)stream, 0, st, nullptr);
+            s = run_batch(jobs, lc, waves, (hipStream_t)stream, 0, st, nullptr, ws, timing);
             if (s != SK_OK) return s;
             for (size_t b = 0; b < jobs.size(); ++b) {
                 const int i = who[b];
@@ -1074,8 +1164,8 @@ sk_status sk_count_batch(const sk_instance* inst, size_t k, const sk_tuning* tun
     for (int i : separate) {
         sk_stats s1;
         sk_u128 o;
-        sk_status s = count_impl(inst[i].n, inst[i].variant, inst[i].flags | SK_ORDERED, tune, stream, nullptr,
-                                 nullptr, &s1, &o);
+        sk_status s = count_impl(inst[i].n, inst[i].variant, inst[i].flags | SK_ORDERED, tune, ws, ws_bytes, stream,
+                                 nullptr, nullptr, &s1, &o, timing);
         if (s != SK_OK) return s;
         result[i] = ((u128)o.hi << 64) | o.lo;
         st.kernel_ms += s1.kernel_ms;
@@ -1096,6 +1186,35 @@ sk_status sk_count_batch(const sk_instance* inst, size_t k, const sk_tuning* tun
     g_stats = st;
     if (stats) *stats = st;
     return SK_OK;
+}
+
+sk_status sk_count_batch(const sk_instance* inst, size_t k, const sk_tuning* tune, void* dev_workspace,
+                         size_t ws_bytes, void* stream, sk_stats* stats, sk_u128* out)
+{
+    return batch_impl(inst, k, tune, dev_workspace, ws_bytes, stream, stats, out, true);
+}
+
+size_t sk_workspace_bytes(const sk_instance* inst, size_t k, const sk_tuning* tune)
+{
+    (void)tune;
+    if (!inst || k == 0) return 0;
+    for (size_t i = 0; i < k; ++i) {
+        Plan P;
+        if (make_plan(inst[i].n, inst[i].variant, P) != SK_OK) return 0;
+    }
+    return kCountWsBytes;
+}
+
+size_t sk_partial_workspace_bytes(int n, int variant, size_t nchunks, int nprimes, const sk_tuning* tune)
+{
+    Plan P;
+    if (make_plan(n, variant, P) != SK_OK || nprimes < 1 || nprimes > 2 * kMaxPrimes) return 0;
+    DeviceCtx* ctx;
+    uint64_t wpl = 0;
+    if (tune && tune->waves_per_launch > 0) wpl = (uint64_t)tune->waves_per_launch;
+    else if (device_ctx(&ctx) == SK_OK) wpl = (uint64_t)ctx->cus * 4 * 8;
+    else return 0;
+    return sum_ws_bytes(true, std::max<uint64_t>(1, std::min<uint64_t>(wpl, nchunks)));
 }
 
 sk_status sk_autotune_batch(const sk_instance* inst, size_t k, void* stream, sk_tuning* best, double* best_rate)
@@ -1178,8 +1297,8 @@ sk_status sk_describe(int n, int variant, sk_plan_desc* out)
 }
 
 sk_status sk_partial_chunks(int n, int variant, int log2_chunks, const uint64_t* chunk_ids, size_t nchunks,
-                            const uint64_t* primes, int nprimes, const sk_tuning* tune, void* stream,
-                            uint64_t* residues_out)
+                            const uint64_t* primes, int nprimes, const sk_tuning* tune, void* dev_workspace,
+                            size_t ws_bytes, void* stream, uint64_t* residues_out)
 {
     if (!chunk_ids || !residues_out || nprimes < 1 || nprimes > 2 * kMaxPrimes) return SK_EINVAL;
     std::vector<uint64_t> dflt;
@@ -1204,6 +1323,8 @@ sk_status sk_partial_chunks(int n, int variant, int log2_chunks, const uint64_t*
     std::vector<uint64_t> res;
     sk_stats st;
     std::memset(&st, 0, sizeof(st));
+    R.ws = dev_workspace;
+    R.ws_bytes = ws_bytes;
     s = run_sum(R, res, st);
     if (s != SK_OK) return s;
     for (size_t c = 0; c < nchunks; ++c)

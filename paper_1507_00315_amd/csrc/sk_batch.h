@@ -23,7 +23,6 @@ namespace sk {
     X(9, 2, 15)
 
 constexpr int kBatchMaxInstances = 16;
-constexpr int kBatchChunkBits = 48;  // item = (instance << 48) | chunk id
 
 struct BatchInstance {
     RevMasks rev;  // reversal weights of the instance (r = 0: none)
@@ -33,12 +32,23 @@ struct BatchInstance {
     double pinv[kMaxPrimes];
 };
 
+// Work items are numbered 0 .. n_items - 1 in the order they are handed out:
+// processing slot s (instances sorted by work per item, largest first) owns
+// items [first[s], first[s + 1]), item first[s] + c being chunk c of instance
+// slot_inst[s].  Residue sums go to acc, kBatchMaxInstances x kMaxPrimes
+// (low word, carries) pairs, instance-major.
 struct BatchArgs {
     BatchInstance inst[kBatchMaxInstances];
-    const uint64_t* items;  // device: n_items work items
-    uint64_t n_items;
-    uint32_t* counter;      // device: next item (set to 0 before the launch)
-    double* out;            // device: n_items x kMaxPrimes residues
+    uint32_t first[kBatchMaxInstances + 1];
+    int32_t slot_inst[kBatchMaxInstances];
+    int32_t nslots;
+    uint32_t n_items;
+    uint32_t* counter;        // device: next item (set to 0 before the launch)
+    unsigned long long* acc;  // device: accumulators (set to 0 before the launch)
 };
+
+// Device workspace of one batched launch: the accumulators, then the counter.
+constexpr size_t kBatchAccBytes = (size_t)kBatchMaxInstances * kMaxPrimes * 2 * sizeof(unsigned long long);
+constexpr size_t kBatchWsBytes = kBatchAccBytes + 256;
 
 }  // namespace sk

@@ -48,6 +48,8 @@ struct ExactArgs {
     uint64_t n_waves;            // waves with work in this launch
     int32_t lane_valid_bits;     // lanes >= 2^lane_valid_bits contribute nothing
     int32_t qb[5];               // product group g covers quads [qb[g], qb[g+1])
+    unsigned long long* acc;     // device: nprimes x (low word, carries) sums of the
+                                 // waves' residues in [0, p); nullptr: one output row per wave
 };
 
 // Reversal weights (Lemma 2.3).  For Skolem and Langford pairings the term
@@ -79,7 +81,12 @@ struct ExactArgsV2 {
     uint64_t chunk_base;         // chunk index of wave 0 (when chunk_ids == nullptr)
     const uint64_t* chunk_ids;   // device array, one chunk id per wave, or nullptr
     uint64_t n_waves;            // waves with work in this launch
+    unsigned long long* acc;     // as ExactArgs::acc
 };
+
+// Device accumulators of one pass: at most this many primes (several launch
+// batches of primes), each a (low word, carries) pair of uint64.
+constexpr int kAccSlots = 16;
 
 // Quad boundaries of the product groups: group gi covers quads
 // [quad_begin(nq, g, gi), quad_begin(nq, g, gi + 1)).

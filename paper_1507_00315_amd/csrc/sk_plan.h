@@ -15,6 +15,11 @@
 //     host-checked bounds of the modular chain hold),
 //   * which factors are stored halved (f_k is even for every x when the
 //     number of pairs L_k at distance d_k is even).
+//
+// The inclusion-exclusion sum (larsen = true) uses the same split with 0/1
+// variables (1: position occupied) and factors N_k = number of occupied
+// pairs at distance d_k, 0 <= N_k <= L_k: nothing is halved, and the walk is
+// the longest possible (no reversal quadruples).
 #pragma once
 
 #include <stdint.h>
@@ -44,7 +49,7 @@ constexpr int kWalkCap = 20;
 
 __host__ __device__ constexpr unsigned __int128 u128_max1(uint64_t x) { return x ? x : 1; }
 
-__host__ __device__ constexpr PlanCE make_plan_ce(int n, int variant, int walk_cap = kWalkCap)
+__host__ __device__ constexpr PlanCE make_plan_ce(int n, int variant, int walk_cap = kWalkCap, bool larsen = false)
 {
     PlanCE P{};
     if (variant < 0 || variant > 2) return P;
@@ -67,7 +72,7 @@ __host__ __device__ constexpr PlanCE make_plan_ce(int n, int variant, int walk_c
         // instead of 7/16.  A job walks 2^(n-9) sign vectors per lane, at
         // least 2^11 for the instances that dominate a count (n >= 20), so
         // the per-job set-up stays below a percent there.
-        const int cap = (variant != 2 && n >= 15 && n - 9 < walk_cap) ? n - 9 : walk_cap;
+        const int cap = (!larsen && variant != 2 && n >= 15 && n - 9 < walk_cap) ? n - 9 : walk_cap;
         const int dmax = P.d[n - 1];
         int w = 0;
         while (w + 1 <= P.m - 1 - P.n_lane && w + 1 <= cap && P.pos[w + 1] + dmax < P.pos[P.m - P.n_lane])
@@ -87,7 +92,7 @@ __host__ __device__ constexpr PlanCE make_plan_ce(int n, int variant, int walk_c
                 ++flen[k];
             }
         }
-        fhalve[k] = (flen[k] % 2 == 0 && flen[k] > 0) ? 1 : 0;
+        fhalve[k] = (!larsen && flen[k] % 2 == 0 && flen[k] > 0) ? 1 : 0;
         fbound[k] = (uint64_t)(flen[k] >> fhalve[k]);
         P.halved += fhalve[k];
     }

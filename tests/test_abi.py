@@ -136,3 +136,52 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
+
+
+def test_workspace_sizes_are_host_only():
+    # counts: the 128-bit accumulators of one batched launch and its counter,
+    # the same for every instance set; 0 on a bad instance
+    a = sk.workspace_bytes([(20, "skolem")])
+    b = sk.workspace_bytes([(16, "skolem"), (15, "langford"), (14, "hooked", sk.ORDERED)])
+    assert a == b and 16 * 4 * 16 <= a <= 4096
+    assert sk.workspace_bytes([(40, "skolem")]) == 0
+    # listed chunks: accumulators, then per wave of a launch one row of up to
+    # four fp64 residues and one chunk id, each region rounded to 256 bytes
+    t = {"waves_per_launch": 64}
+    assert sk.partial_workspace_bytes(20, "skolem", 1000, 2, t) == 256 + 64 * 32 + 512
+    assert sk.partial_workspace_bytes(20, "skolem", 10, 2, t) == 256 + 512 + 256
+    assert sk.partial_workspace_bytes(20, "skolem", 10, 9, t) == 0
+
+
+def _rows(n, variant, C):
+    """Residue row of the ordered count C as the GPU sum delivers it:
+    C * 2^(2n - 1 - halved) modulo each of the count's primes."""
+    import oracle as O
+    O.build(force=False)
+    d = sk.describe(n, variant)
+    primes = O.primes_below(1 << 46, d["primes"])
+    return [C * pow(2, 2 * n - 1 - d["halved"], p) % p for p in primes], primes
+
+
+@pytest.mark.parametrize("variant,n,ordered", [("skolem", 12, 455936), ("skolem", 24, 204776117691241344),
+                                               ("langford", 23, 7598911885030976)])
+def test_corrupted_residue_is_rejected(variant, n, ordered):
+    """A residue set changed in any one prime gives a CRT value that is
+    uniform-looking in [0, prod p); it passes the bound check C <= n! (and the
+    parity check of the reflections) with probability about n! / prod p:
+    2^-63 for n = 12, 2^-12 for n = 24 with two primes.  Seeded corruptions
+    of one residue (plus 1, minus 1, random) must all give SK_ECHECK."""
+    from paper_1507_00315_amd import inputs
+    row, primes = _rows(n, variant, ordered)
+    assert sk.count_combine(n, variant, [row], ordered=True) == ordered
+    rng = inputs.SplitMix64(4000 + n)
+    bad = []
+    for i, p in enumerate(primes):
+        for delta in (1, p - 1, 1 + rng.below(p - 1), 1 + rng.below(p - 1)):
+            r = list(row)
+            r[i] = (r[i] + delta) % p
+            bad.append(r)
+    for r in bad:
+        with pytest.raises(sk.SkolemError) as ei:
+            sk.count_combine(n, variant, [r])
+        assert ei.value.status == -4  # SK_ECHECK

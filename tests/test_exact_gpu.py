@@ -296,3 +296,36 @@ def test_count_parts_reject_bad_splits():
         sk.count_part(16, "skolem", 4, 4)   # part out of range
     with pytest.raises(sk.SkolemError):
         sk.count_part(16, "skolem", 0, 1 << 40)  # more parts than chunks
+
+
+def test_caller_workspace_gives_the_same_results():
+    """Counts and chunk rows with a caller-owned device workspace (a torch
+    tensor sized by sk_workspace_bytes / sk_partial_workspace_bytes) equal
+    those with the library's own; a workspace one byte short is refused with
+    SK_ENOMEM before any work and leaves the outputs untouched."""
+    import ctypes
+    import torch
+    inst = [(16, "skolem"), (15, "langford"), (14, "hooked", sk.ORDERED), (13, "skolem")]
+    nb = sk.workspace_bytes(inst)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    want = [_expected(16, "skolem"), _expected(15, "langford"), _expected(14, "hooked"), 1520280]
+    got, _ = sk.count_batch(inst, workspace=ws)
+    assert got == want
+    assert sk.count_ex(13, "skolem", workspace=ws).count == 1520280
+    ids = inputs.distinct_ids(77, 10, 300)
+    rows = sk.partial_chunks(16, "skolem", 10, ids, PRIMES[:2])
+    pb = sk.partial_workspace_bytes(16, "skolem", len(ids), 2)
+    wp = torch.empty(pb, dtype=torch.uint8, device="cuda")
+    assert sk.partial_chunks(16, "skolem", 10, ids, PRIMES[:2], workspace=wp) == rows
+    # too small: SK_ENOMEM, outputs untouched
+    L = sk.lib()
+    arr = sk._instances(inst)
+    out = (sk.U128 * len(inst))()
+    for o in out:
+        o.lo, o.hi = 7, 7
+    st = L.sk_count_batch(arr, len(inst), None, ctypes.c_void_p(ws.data_ptr()), nb - 1, None, None, out)
+    assert st == -5 and all(o.lo == 7 and o.hi == 7 for o in out)
+    with pytest.raises(sk.SkolemError) as ei:
+        sk.partial_chunks(16, "skolem", 10, ids, PRIMES[:2], workspace=(wp.data_ptr(), pb - 1))
+    assert ei.value.status == -5
+    torch.cuda.synchronize()
