@@ -72,30 +72,33 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 
 /* ------------------------------------------------------------------ problem */
 
+/* Pairs n <= PT_MAXN, positions 1..top with top <= 2 PT_MAXN + 1. */
+#define PT_MAXN 40
+#define PT_MAXTOP (2 * PT_MAXN + 1)
+
 typedef struct {
     int n, m, top;
-    int d[32];
-    int L[32];
-    int start[32][64]; /* ascending placements of pair k */
-    uint64_t pset;
+    int d[PT_MAXN];
+    int L[PT_MAXN];
+    int start[PT_MAXN][PT_MAXTOP]; /* ascending placements of pair k */
+    char in_set[PT_MAXTOP + 2];    /* in_set[p]: position p belongs to P */
 } relaxed;
 
 static int setup(int n, int variant, relaxed *R)
 {
-    if (n < 1 || n > 32 || variant < 0 || variant > 2) return -1;
+    if (n < 1 || n > PT_MAXN || variant < 0 || variant > 2) return -1;
     memset(R, 0, sizeof(*R));
     R->n = n;
     R->top = (variant == 2) ? 2 * n + 1 : 2 * n;
-    if (R->top > 64) return -1;
     for (int p = 1; p <= R->top; ++p) {
         if (variant == 2 && p == 2 * n) continue;
-        R->pset |= 1ull << (p - 1);
+        R->in_set[p] = 1;
         R->m++;
     }
     for (int k = 0; k < n; ++k) {
         R->d[k] = (variant == 1) ? k + 2 : k + 1;
         for (int a = 1; a + R->d[k] <= R->top; ++a)
-            if (((R->pset >> (a - 1)) & 1) && ((R->pset >> (a + R->d[k] - 1)) & 1)) R->start[k][R->L[k]++] = a;
+            if (R->in_set[a] && R->in_set[a + R->d[k]]) R->start[k][R->L[k]++] = a;
         if (R->L[k] == 0) return 1; /* no configuration at all */
     }
     return 0;
@@ -106,7 +109,7 @@ static int energy(const relaxed *R, const int *occ)
 {
     int e = 0;
     for (int p = 1; p <= R->top; ++p)
-        if (((R->pset >> (p - 1)) & 1) && occ[p] == 0) ++e;
+        if (R->in_set[p] && occ[p] == 0) ++e;
     return e;
 }
 
@@ -119,8 +122,8 @@ int orc_energy_histogram(int n, int variant, uint64_t *hist)
     if (rc < 0) return -1;
     memset(hist, 0, sizeof(uint64_t) * (R.top + 1));
     if (rc > 0) return 0; /* Z(0) = 0 */
-    int idx[32] = {0};
-    int occ[66];
+    int idx[PT_MAXN] = {0};
+    int occ[PT_MAXTOP + 2];
     for (;;) {
         memset(occ, 0, sizeof(occ));
         for (int k = 0; k < n; ++k) {
@@ -144,8 +147,8 @@ static uint32_t threshold(double b, int e)
 }
 
 typedef struct {
-    int a[32];
-    int occ[66];
+    int a[PT_MAXN];
+    int occ[PT_MAXTOP + 2];
     int e;
 } chain_state;
 
