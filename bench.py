@@ -19,7 +19,11 @@ Workloads (all inputs are the problem statements themselves: no data files):
   s20    Skolem n = 20;  l20  Langford n = 20
   s12    Skolem n = 12, two primes (the small correctness case)
   s25    Skolem n = 25 (2^49 sign vectors; the paper used four GPUs)
+  all24  every nonzero S(n) and L(n) with n <= 24 in one batched call (one
+         persistent launch per batched group; n <= 11 by separate launches)
   pt     the tempering curve alone (the plain runs' level-moves/s as the value)
+  larsen20  S(20) and L(20) by inclusion-exclusion over the empty positions
+         (the third approach of Sec. 2; 2^40 terms each, no symmetry)
   l28slice  Langford n = 28: a seeded 1/4096 subset of its 2^24 prefix chunks
          (2^43 sign vectors) with the three primes a full count needs; the
          projected full-count time is reported
@@ -51,6 +55,8 @@ WORKLOADS = {
     "l28slice": [("langford", 28)],
     "pt": [],
     "s25": [("skolem", 25)],
+    # the inclusion-exclusion count (third approach of Sec. 2) of S(20) and L(20)
+    "larsen20": [("skolem", 20), ("langford", 20)],
     # every nonzero S(n) and L(n) up to n = 24 (existence: S needs n = 0, 1 mod 4,
     # L needs n = 0, 3 mod 4), largest first
     "all24": sorted([("skolem", n) for n in range(1, 25) if n % 4 in (0, 1)] +
@@ -248,18 +254,29 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def pt_bench(sk, want, plain_iters, learned_iters, ladders: int, learned_cfg: dict, seed: int = 1507,
-             cpu_pt: bool = True):
-    """Tempering estimates (Sec. 3) on the 49-level ladder: relative error
-    against the printed S(20), S(24) and GPU seconds, as a curve over run
-    lengths, for plain uniform moves and with the learned proposal; S(32)
-    beside the paper's own estimate.  Every run first burns in (learned: and
-    trains on) a quarter of its recorded iterations."""
-    betas = config5_ladder()
-    runs = []
+# The paper's own tempering estimates beyond the exact counts (Table 7: S(32),
+# S(33); Table 8: L(31), L(32)), for context beside ours.
+PAPER_PT_ESTIMATES = {("skolem", 32): 2.213e26, ("skolem", 33): 3.614e27, ("langford", 31): 5.381e24,
+                      ("langford", 32): 8.812e25}
 
-    def one(n, name, iters):
-        exact = want.get(("skolem", n))
+
+def pt_bench(sk, want, plain_iters, learned_iters, tuned_iters, ladders: int, learned_cfg: dict, seed: int = 1507,
+             cpu_pt: bool = True):
+    """Tempering estimates (Sec. 3): relative error against the printed S(20),
+    S(24) and GPU seconds, as a curve over run lengths, for plain uniform moves
+    on the 49-level ladder, with the learned proposal on the same ladder, and
+    with plain moves on the ladder tuned by Sec. 3's rule (exchanges accepted
+    at least half the time, as few levels as that takes); per curve the least
+    GPU time that reached 1 % of exact; S(32), S(33), L(31), L(32) beside the
+    paper's estimates.  Every run first burns in (learned: and trains on) a
+    quarter of its recorded iterations; half_z is the equilibration check of
+    each run (its two halves against each other)."""
+    fixed = config5_ladder()
+    runs = []
+    tuned = {}
+
+    def one(variant, n, name, iters, betas):
+        exact = want.get((variant, n))
         kw = dict(ladders=ladders, iterations=iters, seed=seed + n)
         if name == "learned":
             kw["proposal"] = sk.PROPOSAL_LEARNED
@@ -267,49 +284,68 @@ def pt_bench(sk, want, plain_iters, learned_iters, ladders: int, learned_cfg: di
         else:
             kw["burn_in"] = iters // 4
         t0 = time.time()
-        est, se, st = sk.approx(n, "skolem", betas, **kw)
+        est, se, st = sk.approx(n, variant, betas, **kw)
         # gpu_s covers the burn-in (plain) or the sampling phase that feeds the
         # training (learned) too: a quarter of the recorded iterations more
         moves = st["moves"] + ladders * len(betas) * (iters // 4)
-        rec = {"n": n, "proposal": name, "iterations": iters, "ladders": ladders, "estimate": est, "std_error": se,
-               "rel_std_error": se / est if est else None, "gpu_s": st["gpu_ms"] * 1e-3,
-               "wall_s": time.time() - t0, "level_moves": moves,
-               "level_moves_per_gpu_s": moves / max(st["gpu_ms"] * 1e-3, 1e-12)}
+        rec = {"instance": f"{variant}:{n}", "n": n, "proposal": name, "levels": len(betas), "iterations": iters,
+               "ladders": ladders, "estimate": est, "std_error": se, "rel_std_error": se / est if est else None,
+               "half_z": st["half_z"], "gpu_s": st["gpu_ms"] * 1e-3, "wall_s": time.time() - t0,
+               "level_moves": moves, "level_moves_per_gpu_s": moves / max(st["gpu_ms"] * 1e-3, 1e-12)}
         if exact:
             rec["exact"] = exact
             rec["rel_error"] = abs(est - exact) / exact
+        paper = PAPER_PT_ESTIMATES.get((variant, n))
+        if paper:
+            rec["paper_estimate"] = paper
+            rec["rel_diff_from_paper"] = (est - paper) / paper
         if name == "learned":
             j0 = learned_cfg["first_level"]
             rec.update({"train_gpu_s": st["train_ms"] * 1e-3, "learned_moves": st["learned_moves"],
                         "learned_accept_mean": sum(st["learned_accept"][j0:]) / (len(betas) - j0),
                         "plain_accept_mean_same_levels": sum(st["move_accept"][j0:]) / (len(betas) - j0),
                         "train_loss": st["train_loss"]})
-        log(f"pt {name:7s} S({n}) 2^{iters.bit_length() - 1} it: {est:.6g} +- {se:.3g}"
-            + (f"  rel err {rec['rel_error']:.2e}" if exact else "") + f"  gpu {rec['gpu_s']:.3f} s")
+        log(f"pt {name:7s} {variant}({n}) {len(betas)} levels 2^{iters.bit_length() - 1} it: {est:.6g} +- {se:.3g}"
+            + (f"  rel err {rec['rel_error']:.2e}" if exact else "")
+            + (f"  vs paper {rec['rel_diff_from_paper']:+.2%}" if paper else "")
+            + f"  half_z {st['half_z']:+.1f}  gpu {rec['gpu_s']:.3f} s")
         runs.append(rec)
 
-    sk.approx(20, "skolem", betas, ladders=ladders, iterations=1 << 10, seed=seed)  # warm-up, not recorded
+    sk.approx(20, "skolem", fixed, ladders=ladders, iterations=1 << 10, seed=seed)  # warm-up, not recorded
     for n in (20, 24):
+        t0 = time.time()
+        betas, acc = sk.pt_tune_ladder(n, "skolem", fixed[-1], target=0.5, max_levels=64, ladders=256,
+                                       pilot_iterations=1 << 14, seed=seed)
+        tuned[n] = {"betas": betas, "swap_accept": acc, "tuning_wall_s": time.time() - t0}
+        log(f"tuned ladder S({n}): {len(betas)} levels, min exchange acceptance {min(acc):.3f} "
+            f"({time.time() - t0:.1f} s)")
         for it in plain_iters:
-            one(n, "plain", it)
+            one("skolem", n, "plain", it, fixed)
         for it in learned_iters:
-            one(n, "learned", it)
-    one(32, "plain", plain_iters[-1])
-    if learned_iters:
-        one(32, "learned", learned_iters[-1])
+            one("skolem", n, "learned", it, fixed)
+        for it in tuned_iters:
+            one("skolem", n, "plain_tuned_ladder", it, betas)
+    for variant, n in PAPER_PT_ESTIMATES:
+        one(variant, n, "plain", plain_iters[-1], fixed)
+    # per curve: the least GPU time whose estimate was within 1 % of exact
+    to_1pct = {}
+    for r in runs:
+        if r.get("rel_error") is not None and r["rel_error"] <= 0.01:
+            key = f"{r['instance']} {r['proposal']}"
+            to_1pct[key] = min(to_1pct.get(key, float("inf")), r["gpu_s"])
     cpu = None
     if cpu_pt:
         import oracle as O
         O.build(force=False)
         iters = 1 << 20
         t0 = time.time()
-        O.pt_ladder(32, "skolem", betas, iters, seed, ladder=0, schedule="even_odd")
+        O.pt_ladder(32, "skolem", fixed, iters, seed, ladder=0, schedule="even_odd")
         dt = time.time() - t0
-        cpu = {"value": iters * len(betas) / dt, "unit": "level-moves/s", "cores": 1, "kind": "oracle",
-               "cpu": cpu_model(), "sample": f"one ladder of S(32), {len(betas)} levels, 2^20 iterations, {dt:.1f} s"}
-    return {"ladder": "beta = 0, then 48 geometric levels 0.05 * 120^(j/47)", "levels": len(betas),
-            "learned_config": {k: v for k, v in learned_cfg.items() if k != "params"}, "runs": runs,
-            "paper_S32_estimate": 2.2e26, "cpu_baseline": cpu}
+        cpu = {"value": iters * len(fixed) / dt, "unit": "level-moves/s", "cores": 1, "kind": "oracle",
+               "cpu": cpu_model(), "sample": f"one ladder of S(32), {len(fixed)} levels, 2^20 iterations, {dt:.1f} s"}
+    return {"ladder": "beta = 0, then 48 geometric levels 0.05 * 120^(j/47)", "levels": len(fixed),
+            "tuned_ladders": tuned, "learned_config": {k: v for k, v in learned_cfg.items() if k != "params"},
+            "runs": runs, "gpu_s_to_1pct": to_1pct, "cpu_baseline": cpu}
 
 
 def main():
@@ -326,7 +362,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-pt", action="store_true", help="skip the tempering estimates")
     ap.add_argument("--pt-plain-log2", default="14,16,18,20,21", help="log2 recorded iterations, plain runs")
-    ap.add_argument("--pt-learned-log2", default="14,16,18", help="log2 recorded iterations, learned runs")
+    ap.add_argument("--pt-learned-log2", default="16,18,20,21", help="log2 recorded iterations, learned runs")
+    ap.add_argument("--pt-tuned-log2", default="18,20,21", help="log2 recorded iterations, tuned-ladder runs")
     ap.add_argument("--pt-ladders", type=int, default=1024)
     ap.add_argument("--pt-learned-every", type=int, default=256)
     ap.add_argument("--pt-learned-first", type=int, default=36)
@@ -363,7 +400,8 @@ def main():
         sync()
         t0 = time.perf_counter()
         pt = pt_bench(sk, want, [1 << int(x) for x in args.pt_plain_log2.split(",")],
-                      [1 << int(x) for x in args.pt_learned_log2.split(",") if x], args.pt_ladders, learned_cfg,
+                      [1 << int(x) for x in args.pt_learned_log2.split(",") if x],
+                      [1 << int(x) for x in args.pt_tuned_log2.split(",") if x], args.pt_ladders, learned_cfg,
                       cpu_pt=not args.no_cpu_baseline)
         sync()
         elapsed = time.perf_counter() - t0
@@ -379,7 +417,7 @@ def main():
     tuning = {"log2_chunk_terms": args.log2_chunk, "kernel": args.kernel, "waves_per_launch": args.waves}
     if args.workload == "s12":
         tuning["primes"] = 2
-    batched = args.workload in ("batch", "mixed") and not args.separate
+    batched = args.workload in ("batch", "mixed", "all24") and not args.separate
 
     slice_ids = None
     if args.workload == "l28slice":
@@ -441,7 +479,10 @@ def main():
             return False
 
         for v, n in instances:
-            r = sk.count_ex(n, v, ordered=(v == "hooked"), tuning=tuning, progress=progress)
+            if args.workload.startswith("larsen"):
+                r = sk.count_larsen(n, v, ordered=(v == "hooked"), tuning=tuning)
+            else:
+                r = sk.count_ex(n, v, ordered=(v == "hooked"), tuning=tuning, progress=progress)
             ok = want.get((v, n))
             res.append((v, n, r.count, r.stats, None if ok is None else (ok == r.count)))
             log(f"[{tag}] {v} n={n}: {r.count}  kernel {r.stats['kernel_ms']:.1f} ms  "
@@ -450,7 +491,7 @@ def main():
         return res
 
     launch_waves = args.waves
-    if batched and not args.no_autotune and not args.log2_chunk:
+    if args.workload in ("batch", "mixed") and batched and not args.no_autotune and not args.log2_chunk:
         t0 = time.time()
         best, rate = sk.autotune_batch([(n, v) for v, n in instances])
         launch_waves = best["waves_per_launch"]
@@ -501,6 +542,13 @@ def main():
             t = results[0][1 + i][3]["terms"]
             legs.append((f"{sl['variant']}:24 slice", f"exact_v2_kernel<{sk.VARIANTS[sl['variant']]},24>", t,
                          per * t, rg * t, 1 + i))
+    elif args.workload.startswith("larsen"):
+        for i, (v, n) in enumerate(instances):
+            d = sk.describe(n, v, larsen=True)
+            d["primes_used"] = d["primes"]
+            t = results[0][i][3]["terms"]
+            legs.append((f"{v}:{n} inclusion-exclusion", sk.kernel_name(results[0][i][3]["kernel_variant"]), t,
+                         valu_per_term(d) * t, ring_ops_per_term(n, d["primes"]) * t, i))
     else:
         for i, (v, n) in enumerate(instances):
             per, terms, rg = design_instr(v, n, True)
@@ -541,6 +589,8 @@ def main():
     elif batched:
         covered = sum(1 << (2 * n - 1) for v, n in instances) + sum(results[0][1 + i][3]["terms"]
                                                                      for i in range(len(n24)))
+    elif args.workload.startswith("larsen"):
+        covered = terms_per_step
     else:
         covered = sum(1 << (2 * n - 1) for v, n in instances)
     config = {"workload": args.workload,
@@ -584,12 +634,13 @@ def main():
                                    "terms_per_chunk": terms_per_step // len(slice_ids), "seed": 1507,
                                    "projected_full_count_s": kms * 1e-3 * full_chunks / len(slice_ids),
                                    "projected_full_count_wall_s": elapsed / args.steps * full_chunks / len(slice_ids)}
-    if batched and not args.no_pt:
+    if args.workload in ("batch", "mixed") and batched and not args.no_pt:
         learned_cfg = dict(hidden1=256, hidden2=256, first_level=args.pt_learned_first,
                            plain_per_learned=args.pt_learned_every, snapshots=8, train_steps=400, minibatch=1024,
                            lr=1e-3, init_seed=1)
         line["pt"] = pt_bench(sk, want, [1 << int(x) for x in args.pt_plain_log2.split(",")],
-                              [1 << int(x) for x in args.pt_learned_log2.split(",") if x], args.pt_ladders,
+                              [1 << int(x) for x in args.pt_learned_log2.split(",") if x],
+                              [1 << int(x) for x in args.pt_tuned_log2.split(",") if x], args.pt_ladders,
                               learned_cfg, cpu_pt=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

@@ -88,12 +88,16 @@ typedef struct { uint64_t lo, hi; } sk_u128;
  *                      whose product exceeds n! * 2^8 (n! bounds every count)
  *   kernel           : kernel body: 0 = the tuned body when built for the
  *                      instance, else the reference; 1 = reference; 2 = tuned
- *                      (SK_ENOLIB if not built)                                */
+ *                      (SK_ENOLIB if not built)
+ *   primes_per_item  : batched launch: 0 = every work item (chunk) takes all
+ *                      of its instance's primes; 1 = one prime per work item
+ *                      (where that kernel is built; else 0)                    */
 typedef struct {
     int log2_chunk_terms;
     int waves_per_launch;
     int primes;
     int kernel;
+    int primes_per_item;
 } sk_tuning;
 
 /* One instance of a batched count. */
@@ -146,8 +150,25 @@ sk_status sk_count_ex(int n, int variant, unsigned flags, const sk_tuning *tune,
                       sk_stats *stats, sk_u128 *out);
 
 /*
- * sk_workspace_bytes -- device workspace that sk_count_ex, sk_count_part and
- * sk_count_batch need for these k instances and launch shape: the 128-bit
+ * sk_count_larsen -- the same exact count by the third approach of Sec. 2,
+ * inclusion-exclusion over the positions a placement leaves empty: with the
+ * universe of all placements of the n pairs inside the position set
+ * (overlaps allowed) and A_i the placements avoiding position i,
+ *     C(n) = sum_{S subset of P} (-1)^|S| prod_k N_k(P \ S),
+ * N_k(T) = number of a with a, a + d_k in T.  The 2^(2n) terms are visited in
+ * Gray-code order on the GPU (occupancy bits instead of signs; nothing is
+ * halved and no symmetry is used) and summed modulo the same primes as
+ * sk_count.  An independent cross-check of sk_count.  Arguments, flags
+ * (SK_NO_SYMMETRY has no effect), errors: as sk_count_ex; SK_ENOLIB where
+ * the instance shape has no kernel (the reference body covers every n).
+ */
+sk_status sk_count_larsen(int n, int variant, unsigned flags, const sk_tuning *tune,
+                          void *dev_workspace, size_t ws_bytes, void *stream,
+                          sk_stats *stats, sk_u128 *out);
+
+/*
+ * sk_workspace_bytes -- device workspace that sk_count_ex, sk_count_larsen,
+ * sk_count_part and sk_count_batch need for these k instances and launch shape: the 128-bit
  * per-prime accumulators of the on-device reduction (Sec. 2.2: the parts'
  * results are put together at the end) and the work counter of the batched
  * launch.  0 on bad input.  Host only.
@@ -189,13 +210,15 @@ sk_status sk_count_combine(int n, int variant, unsigned flags, const uint64_t *r
                            sk_u128 *out);
 
 /*
- * sk_count_batch -- exact counts of k instances (Sec. 2) in one persistent
- * kernel launch: wavefronts pull (instance, chunk) work items from one global
- * queue, so instances of very different size share the GPU without a tail per
- * instance.  The batched launch holds the tuned bodies of Skolem n = 16, 17,
- * 20, 21, Langford n = 15, 16, 19, 20 and hooked n = 14, 15; other instances,
- * and instances with tune->kernel == 1 or a larger prime count, are counted
- * by separate launches in the same call.
+ * sk_count_batch -- exact counts of k instances (Sec. 2) in persistent kernel
+ * launches: wavefronts pull (instance, chunk) work items from one global queue,
+ * so instances of very different size share the GPU without a tail per
+ * instance.  The instances are grouped (n = 12, 13; the mixed set Skolem 16,
+ * 17, 20, 21, Langford 15, 16, 19, 20, hooked 14, 15; the other 14 <= n <= 21;
+ * 22 <= n <= 25: the persistent kernel of a group holds the tuned body of each
+ * of its instances), one launch per group that holds instances (at most 16);
+ * instances outside the groups, and instances with tune->kernel == 1 or a
+ * larger prime count, are counted by separate launches in the same call.
  *   inst  : k instances (k >= 1); out: k counts, in order
  *   tune  : NULL = the shape found by sk_autotune_batch for this instance set
  *           (cached per GPU model), else log2_chunk_terms (sign vectors per work
@@ -213,12 +236,14 @@ sk_status sk_count_batch(const sk_instance *inst, size_t k, const sk_tuning *tun
                          sk_stats *stats, sk_u128 *out);
 
 /*
- * sk_autotune_batch -- times the batched launch of these instances on 1/16 of
- * their work for a grid of (sign vectors per work item) x (waves per SIMD),
- * stores the fastest in the cache file ($SK_TUNE_CACHE, default
- * ~/.cache/skolem_mi355x_tune.txt) keyed by GPU model and instance set, and
- * returns it.  best_rate (nullable) receives sign vectors per second.
- * Errors: SK_ENOLIB if an instance is not compiled into the batched launch.
+ * sk_autotune_batch -- times the batched launch of these instances, group by
+ * group, on a fraction of their work (about 2^36 sign vectors, at most 1/16)
+ * for a grid of (sign vectors per work item) x (waves per SIMD) x (primes per
+ * work item, where built), stores the fastest shape of each group in the cache
+ * file ($SK_TUNE_CACHE, default ~/.cache/skolem_mi355x_tune.txt) keyed by GPU
+ * model and instance set, and returns that of the group with the most sign
+ * vectors.  best_rate (nullable) receives its sign vectors per second.
+ * Errors: SK_ENOLIB if an instance has no batched kernel.
  */
 sk_status sk_autotune_batch(const sk_instance *inst, size_t k, void *stream, sk_tuning *best,
                             double *best_rate);
@@ -343,6 +368,16 @@ typedef struct {
     uint64_t learned_moves;    /* learned moves per chain of a learned level */
     double train_ms;           /* GPU time of the training phase (included in gpu_ms) */
     double train_loss;         /* mean cross-entropy of the last Adam minibatch */
+    /* Equilibration check: the estimate and its standard error from the first
+     * and from the second half of the recorded iterations (for a learned run,
+     * split at the first learned move past the middle), and
+     * half_z = (second - first) / sqrt(se_first^2 + se_second^2).  The
+     * standard error of sk_approx measures the spread between ladders only;
+     * chains that are still equilibrating bias every ladder the same way and
+     * show as |half_z| well above 2 (0 when the run is too short to split). */
+    double estimate_half[2];
+    double std_error_half[2];
+    double half_z;
 } sk_pt_stats;
 
 /* Energy bins per level: 2n + 1 (Skolem, Langford) or 2n + 2 (hooked); -1 on
@@ -374,6 +409,27 @@ sk_status sk_pt_run(int n, int variant, const sk_pt_params *p, void *stream, uin
  */
 sk_status sk_approx(int n, int variant, const sk_pt_params *p, void *stream, double *estimate,
                     double *std_error, sk_pt_stats *stats);
+
+/*
+ * sk_pt_tune_ladder -- inverse temperatures 0 = beta_0 < ... < beta_{M-1} =
+ * beta_max chosen as the last paragraph of Sec. 3 prescribes: every exchange
+ * of neighbouring levels is accepted with probability at least `target` (the
+ * paper: one half), with no more levels than that takes.  Starting from
+ * {0, beta_max}, pilot runs (plain moves, `pilot_iterations` burn-in and as
+ * many recorded iterations on `ladders` ladders, Philox key seed + round)
+ * measure the acceptance of each neighbouring pair; a level is inserted in
+ * the middle of every pair below the target (the arithmetic mean next to
+ * beta = 0, the geometric mean elsewhere), lowest acceptance first, until no
+ * pair is below the target or max_levels (<= 64) is reached.
+ *   beta_out    : max_levels doubles, the ladder (levels_out of them)
+ *   accept_out  : NULL or max_levels doubles, the last pilot's acceptance of
+ *                 the exchange (j, j+1); if max_levels stopped the search,
+ *                 some are below the target
+ * Errors: SK_EINVAL (bad instance or arguments), SK_EDEVICE.
+ */
+sk_status sk_pt_tune_ladder(int n, int variant, double beta_max, double target, int max_levels,
+                            int ladders, uint64_t pilot_iterations, uint64_t seed, void *stream,
+                            double *beta_out, int *levels_out, double *accept_out);
 
 /* ------------------------------------------------------------------------
  * The proposal network (fp32, device-resident while a call runs).
@@ -449,6 +505,10 @@ typedef struct {
 } sk_plan_desc;
 
 sk_status sk_describe(int n, int variant, sk_plan_desc *out);
+
+/* The same for the inclusion-exclusion sum of sk_count_larsen (0/1 variables:
+ * nothing halved, symmetric = reversal_quads = 0).  Host only. */
+sk_status sk_describe_larsen(int n, int variant, sk_plan_desc *out);
 
 /* Describes a status code (static string). */
 const char *sk_strerror(sk_status s);

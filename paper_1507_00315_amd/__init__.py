@@ -46,7 +46,7 @@ class U128(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("log2_chunk_terms", ctypes.c_int), ("waves_per_launch", ctypes.c_int),
-                ("primes", ctypes.c_int), ("kernel", ctypes.c_int)]
+                ("primes", ctypes.c_int), ("kernel", ctypes.c_int), ("primes_per_item", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -93,7 +93,9 @@ class PtStats(ctypes.Structure):
                 ("swap_accept", ctypes.c_double * 64), ("ratio", ctypes.c_double * 64),
                 ("gpu_ms", ctypes.c_double), ("wall_ms", ctypes.c_double), ("moves", ctypes.c_uint64),
                 ("levels", ctypes.c_int), ("ladders", ctypes.c_int), ("learned_accept", ctypes.c_double * 64),
-                ("learned_moves", ctypes.c_uint64), ("train_ms", ctypes.c_double), ("train_loss", ctypes.c_double)]
+                ("learned_moves", ctypes.c_uint64), ("train_ms", ctypes.c_double), ("train_loss", ctypes.c_double),
+                ("estimate_half", ctypes.c_double * 2), ("std_error_half", ctypes.c_double * 2),
+                ("half_z", ctypes.c_double)]
 
     def as_dict(self) -> Dict:
         M = self.levels
@@ -102,7 +104,8 @@ class PtStats(ctypes.Structure):
                 "gpu_ms": self.gpu_ms, "wall_ms": self.wall_ms, "moves": int(self.moves),
                 "levels": M, "ladders": self.ladders, "learned_accept": list(self.learned_accept[:M]),
                 "learned_moves": int(self.learned_moves), "train_ms": self.train_ms,
-                "train_loss": self.train_loss}
+                "train_loss": self.train_loss, "estimate_half": list(self.estimate_half),
+                "std_error_half": list(self.std_error_half), "half_z": self.half_z}
 
 
 PROGRESS_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64)
@@ -118,6 +121,13 @@ def lib() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_1507_00315_amd.build` "
                            "(there is no CPU fallback)")
+    # torch (the device-memory and stream plumbing) ships its own HIP runtime
+    # under the same soname; loading it first makes the library bind to that
+    # copy, so a process that uses both holds one HIP runtime, not two.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     c_int, c_uint, c_size, vp = ctypes.c_int, ctypes.c_uint, ctypes.c_size_t, ctypes.c_void_p
     u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -134,13 +144,19 @@ def lib() -> ctypes.CDLL:
                                 c_size, vp, PROGRESS_FN, vp, ctypes.POINTER(Stats), u64p]
     L.sk_count_combine.argtypes = [c_int, c_int, c_uint, u64p, ctypes.c_uint64, ctypes.POINTER(U128)]
     L.sk_describe.argtypes = [c_int, c_int, ctypes.POINTER(PlanDesc)]
+    L.sk_describe_larsen.argtypes = [c_int, c_int, ctypes.POINTER(PlanDesc)]
     L.sk_pt_bins.argtypes = [c_int, c_int]
     L.sk_pt_run.argtypes = [c_int, c_int, ctypes.POINTER(PtParams), vp, u64p, u64p, u64p,
                             ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)]
+    L.sk_pt_tune_ladder.argtypes = [c_int, c_int, ctypes.c_double, ctypes.c_double, c_int, c_int, ctypes.c_uint64,
+                                    ctypes.c_uint64, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int),
+                                    ctypes.POINTER(ctypes.c_double)]
     L.sk_approx.argtypes = [c_int, c_int, ctypes.POINTER(PtParams), vp, ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(PtStats)]
     L.sk_count_batch.argtypes = [ctypes.POINTER(Instance), c_size, ctypes.POINTER(Tuning), vp, c_size, vp,
                                  ctypes.POINTER(Stats), ctypes.POINTER(U128)]
+    L.sk_count_larsen.argtypes = [c_int, c_int, c_uint, ctypes.POINTER(Tuning), vp, c_size, vp,
+                                  ctypes.POINTER(Stats), ctypes.POINTER(U128)]
     L.sk_workspace_bytes.argtypes = [ctypes.POINTER(Instance), c_size, ctypes.POINTER(Tuning)]
     L.sk_workspace_bytes.restype = c_size
     L.sk_partial_workspace_bytes.argtypes = [c_int, c_int, c_size, c_int, ctypes.POINTER(Tuning)]
@@ -166,6 +182,7 @@ def lib() -> ctypes.CDLL:
     L.sk_kernel_name.argtypes = [c_int]
     L.sk_kernel_name.restype = ctypes.c_char_p
     for fn in ("sk_set_device", "sk_count", "sk_count_ex", "sk_sign_sum_residues", "sk_partial_chunks",
+               "sk_count_larsen", "sk_describe_larsen", "sk_pt_tune_ladder",
                "sk_max_chunk_bits", "sk_describe", "sk_count_batch", "sk_autotune_batch", "sk_pt_bins",
                "sk_pt_run", "sk_approx", "sk_last_stats", "sk_count_part", "sk_count_combine", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
                "sk_mlp_mh_step"):
@@ -175,7 +192,7 @@ def lib() -> ctypes.CDLL:
 
 
 EXPORTED = ["sk_set_device", "sk_count", "sk_count_ex", "sk_count_batch", "sk_autotune_batch", "sk_pt_bins",
-            "sk_workspace_bytes", "sk_partial_workspace_bytes",
+            "sk_workspace_bytes", "sk_partial_workspace_bytes", "sk_count_larsen", "sk_describe_larsen", "sk_pt_tune_ladder",
             "sk_pt_run", "sk_approx", "sk_sign_sum_residues", "sk_partial_chunks",
             "sk_max_chunk_bits", "sk_describe", "sk_strerror", "sk_last_error", "sk_u128_to_decimal", "sk_kernel_name",
             "sk_last_stats", "sk_count_part", "sk_count_combine", "sk_mlp_param_count", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
@@ -217,7 +234,7 @@ def _tuning(tuning: Optional[Dict]) -> Optional[Tuning]:
     if not tuning:
         return None
     return Tuning(int(tuning.get("log2_chunk_terms", 0)), int(tuning.get("waves_per_launch", 0)),
-                  int(tuning.get("primes", 0)), int(tuning.get("kernel", 0)))
+                  int(tuning.get("primes", 0)), int(tuning.get("kernel", 0)), int(tuning.get("primes_per_item", 0)))
 
 
 def set_device(device: int) -> None:
@@ -257,6 +274,22 @@ def count_ex(n: int, variant="skolem", ordered: bool = False, verify: bool = Fal
     status = lib().sk_count_ex(n, _variant(variant), flags, ctypes.byref(t) if t else None, wp, wb,
                                _stream_handle(stream), cb, None, ctypes.byref(st), ctypes.byref(out))
     _check(status, f"sk_count_ex(n={n}, variant={variant})")
+    return CountResult(out.value(), st.as_dict())
+
+
+def count_larsen(n: int, variant="skolem", ordered: bool = False, verify: bool = False,
+                 no_shortcut: bool = False, tuning: Optional[Dict] = None, stream=None,
+                 workspace=None) -> CountResult:
+    """Exact count by inclusion-exclusion over the empty positions (the third
+    approach of Sec. 2), with launch statistics (sk_count_larsen)."""
+    flags = _flags(ordered, verify, no_shortcut, False)
+    out = U128()
+    st = Stats()
+    t = _tuning(tuning)
+    wp, wb = _workspace(workspace)
+    _check(lib().sk_count_larsen(n, _variant(variant), flags, ctypes.byref(t) if t else None, wp, wb,
+                                 _stream_handle(stream), ctypes.byref(st), ctypes.byref(out)),
+           f"sk_count_larsen(n={n}, variant={variant})")
     return CountResult(out.value(), st.as_dict())
 
 
@@ -349,7 +382,8 @@ def autotune_batch(instances, stream=None):
     rate = ctypes.c_double()
     _check(lib().sk_autotune_batch(arr, len(instances), _stream_handle(stream), ctypes.byref(best),
                                    ctypes.byref(rate)), "sk_autotune_batch")
-    return {"log2_chunk_terms": best.log2_chunk_terms, "waves_per_launch": best.waves_per_launch}, rate.value
+    return {"log2_chunk_terms": best.log2_chunk_terms, "waves_per_launch": best.waves_per_launch,
+            "primes_per_item": best.primes_per_item}, rate.value
 
 
 def _u64_array(values: Sequence[int]):
@@ -403,10 +437,12 @@ def max_chunk_bits(n: int, variant) -> int:
     return int(lib().sk_max_chunk_bits(n, _variant(variant)))
 
 
-def describe(n: int, variant) -> Dict:
-    """Variable split and product grouping the library uses for (n, variant)."""
+def describe(n: int, variant, larsen: bool = False) -> Dict:
+    """Variable split and product grouping the library uses for (n, variant):
+    of the sign sum, or with larsen of the inclusion-exclusion sum."""
     d = PlanDesc()
-    _check(lib().sk_describe(n, _variant(variant), ctypes.byref(d)), "sk_describe")
+    fn = lib().sk_describe_larsen if larsen else lib().sk_describe
+    _check(fn(n, _variant(variant), ctypes.byref(d)), "sk_describe")
     out = {name: getattr(d, name) for name, _ in d._fields_ if name != "slot_factor"}
     out["slot_factor"] = [int(x) for x in d.slot_factor[: 4 * d.quads]]
     return out
@@ -469,6 +505,19 @@ def pt_run(n: int, variant, betas: Sequence[float], ladders: int, iterations: in
             "swap_accept": [[int(sw[l * M + j]) for j in range(M)] for l in range(ladders)],
             "state": [[[int(state[(l * M + j) * n + k]) for k in range(n)] for j in range(M)] for l in range(ladders)],
             "energy": [[int(energy[l * M + j]) for j in range(M)] for l in range(ladders)]}
+
+
+def pt_tune_ladder(n: int, variant, beta_max: float, target: float = 0.5, max_levels: int = 64, ladders: int = 256,
+                   pilot_iterations: int = 1 << 14, seed: int = 1, stream=None):
+    """Inverse temperatures from 0 to beta_max with every neighbouring
+    exchange accepted at least `target` of the time (Sec. 3): (betas, the last
+    pilot's exchange acceptances)."""
+    b = (ctypes.c_double * max_levels)()
+    acc = (ctypes.c_double * max_levels)()
+    m = ctypes.c_int()
+    _check(lib().sk_pt_tune_ladder(n, _variant(variant), beta_max, target, max_levels, ladders, pilot_iterations, seed,
+                                   _stream_handle(stream), b, ctypes.byref(m), acc), "sk_pt_tune_ladder")
+    return [b[j] for j in range(m.value)], [acc[j] for j in range(m.value - 1)]
 
 
 def approx(n: int, variant, betas: Sequence[float], ladders: int, iterations: int, seed: int,
@@ -582,7 +631,7 @@ def last_stats_dict(st: Stats) -> Dict:
     return st.as_dict()
 
 
-__all__ = ["count", "count_ex", "count_batch", "workspace_bytes", "partial_workspace_bytes", "autotune_batch", "pt_run", "approx", "pt_bins", "sign_sum_residues",
+__all__ = ["pt_tune_ladder", "count", "count_ex", "count_larsen", "count_batch", "workspace_bytes", "partial_workspace_bytes", "autotune_batch", "pt_run", "approx", "pt_bins", "sign_sum_residues",
            "partial_chunks", "last_stats", "count_part", "count_combine", "max_chunk_bits", "set_device", "mlp_param_count", "mlp_init", "mlp_forward",
            "mlp_loss_grad", "mlp_train", "mlp_mh_step", "PROPOSAL_UNIFORM", "PROPOSAL_LEARNED",
            "SkolemError", "SKOLEM", "LANGFORD", "HOOKED", "lib", "EXPORTED"]

@@ -19,12 +19,19 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libskolem.so")
 
-SOURCES = ["host.cpp", "pt_host.cpp", "mlp_host.cpp", "exact_v1.hip", "exact_batch.hip", "pt.hip", "mlp.hip"]
+SOURCES = ["host.cpp", "pt_host.cpp", "mlp_host.cpp", "exact_v1.hip", "pt.hip", "mlp.hip"]
+
+# Persistent batched kernels: (group, primes per work item) per translation
+# unit; group 1 (the mixed-instance workload) also with one prime per work
+# item, an axis of the autotuner.
+BATCH_UNITS = [(0, 0), (1, 0), (1, 1), (2, 0), (3, 0)]
 
 # Tuned kernel specialisations: (variant, n_min, n_max) per translation unit,
 # so they compile in parallel.
 V2_UNITS = [(v, lo, hi) for v in (0, 1, 2) for lo, hi in ((12, 15), (16, 18), (19, 21), (22, 24),
                                                            (25, 27), (28, 30), (31, 32))]
+# The inclusion-exclusion sum (Sec. 2, third approach), tuned body: n = 12..22.
+LARSEN_UNITS = [(v, lo, hi) for v in (0, 1, 2) for lo, hi in ((12, 16), (17, 19), (20, 22))]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -54,6 +61,11 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for v, lo, hi in V2_UNITS:
         units.append(("exact_v2_inst.hip", f"exact_v2_{v}_{lo}_{hi}.o",
                       [f"-DSK_V2_VARIANT={v}", f"-DSK_V2_NMIN={lo}", f"-DSK_V2_NMAX={hi}"]))
+    for g, ppi in BATCH_UNITS:
+        units.append(("exact_batch.hip", f"exact_batch_{g}_{ppi}.o", [f"-DSK_BATCH_GROUP={g}", f"-DSK_BATCH_PPI={ppi}"]))
+    for v, lo, hi in LARSEN_UNITS:
+        units.append(("exact_v2_inst.hip", f"larsen_v2_{v}_{lo}_{hi}.o",
+                      [f"-DSK_V2_VARIANT={v}", f"-DSK_V2_NMIN={lo}", f"-DSK_V2_NMAX={hi}", "-DSK_V2_LARSEN=1"]))
     for src, oname, defs in units:
         obj = os.path.join(objdir, oname)
         objs.append(obj)

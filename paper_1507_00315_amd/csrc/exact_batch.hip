@@ -1,43 +1,80 @@
 // Persistent batched launch of the tuned exact kernel: many instances (n,
 // variant) of uneven size in one kernel.  Wavefronts pull work items (instance,
-// chunk) from a global atomic counter until the list is exhausted; each item is
-// one chunk of one instance, evaluated by the specialisation compiled for that
-// instance (a wave-uniform branch).  Reduction: the wave's residues (butterfly
-// over the lanes) go into a per-workgroup LDS table, one (low word, carries)
-// pair per instance and prime; when the workgroup's waves have left the loop
-// the table is added to the device accumulators.  The host reads one 128-bit
-// sum per instance and prime and reduces it modulo the prime.
+// chunk[, prime]) from a global atomic counter until the list is exhausted;
+// each item is one chunk of one instance, evaluated by the specialisation
+// compiled for that instance (a wave-uniform branch).  Reduction: the wave's
+// residues (butterfly over the lanes) go into a per-workgroup LDS table, one
+// (low word, carries) pair per instance and prime; when the workgroup's waves
+// have left the loop the table is added to the device accumulators.  The host
+// reads one 128-bit sum per instance and prime and reduces it modulo the prime.
 //
-// The set of specialisations compiled into this kernel is SK_BATCH_CASES (the
-// host keeps the same list); other instances are counted by separate launches.
-#include <algorithm>
-
+// The build compiles this file once per group and primes-per-item setting,
+//   -DSK_BATCH_GROUP=g -DSK_BATCH_PPI=p,
+// each unit holding the tuned body of every (variant, n) of group g
+// (batch_group_of in sk_batch.h) and registering its launcher with the host.
 #include "exact_v2_body.h"
 #include "sk_batch.h"
+
+#ifndef SK_BATCH_GROUP
+#define SK_BATCH_GROUP 1
+#endif
+#ifndef SK_BATCH_PPI
+#define SK_BATCH_PPI 0
+#endif
 
 namespace sk {
 
 constexpr int kBatchInner = 4;
 
 template <int V, int N>
-__device__ __forceinline__ void batch_case(uint64_t chunk, const BatchInstance& in, unsigned long long* tab)
+constexpr bool batch_supported()
 {
-    constexpr int P = primes_for(N);
+    constexpr PlanCE P = make_plan_ce(N, V);
+    return P.ok && P.n_lane == 6 && P.n_walk >= kBatchInner + 1;
+}
+
+// One work item of instance `in`: chunk `item` with all its primes (PPI = 0),
+// or chunk item / P with prime item % P (PPI = 1).  Lane 0 adds the residues
+// to the workgroup's table row `tab` of the instance.
+template <int PPI, int V, int N>
+__device__ __forceinline__ void batch_case(uint64_t item, const BatchInstance& in, unsigned long long* tab)
+{
+    constexpr int PN = primes_for(N);
+    constexpr int P = PPI == 1 ? 1 : PN;
+    const uint64_t chunk = PPI == 1 ? item / PN : item;
+    const int p0 = PPI == 1 ? (int)(item % PN) : 0;  // wave-uniform
     double pr[P], pinv[P], res[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-        pr[i] = in.prime[i];
-        pinv[i] = in.pinv[i];
+        pr[i] = in.prime[p0 + i];
+        pinv[i] = in.pinv[p0 + i];
     }
     exact_v2_chunk<V, N, P, kBatchInner>(chunk, in.jb, in.rev, pr, pinv, res);
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-        for (int i = 0; i < P; ++i) add_u128(tab + 2 * i, canonical_residue(res[i], pr[i], pinv[i]));
+        for (int i = 0; i < P; ++i) add_u128(tab + 2 * (p0 + i), canonical_residue(res[i], pr[i], pinv[i]));
+    }
+}
+
+// Branch to the specialisation of (V, n) among the n in [N, group G's highest]
+// that belong to group G.
+template <int G, int PPI, int V, int N>
+__device__ __forceinline__ void dispatch_n(int n, uint64_t item, const BatchInstance& in, unsigned long long* tab)
+{
+    if constexpr (N <= batch_group_hi(G)) {
+        if constexpr (batch_group_of(V, N) == G && batch_supported<V, N>()) {
+            if (n == N) {
+                batch_case<PPI, V, N>(item, in, tab);
+                return;
+            }
+        }
+        dispatch_n<G, PPI, V, N + 1>(n, item, in, tab);
     }
 }
 
 constexpr int kBatchTab = kBatchMaxInstances * kMaxPrimes * 2;
 
+template <int G, int PPI>
 __global__ void __launch_bounds__(256) exact_batch_kernel(const BatchArgs a)
 {
     __shared__ unsigned long long tab[kBatchTab];
@@ -57,18 +94,15 @@ __global__ void __launch_bounds__(256) exact_batch_kernel(const BatchArgs a)
         int s = 0;
         while (s + 1 < a.nslots && idx >= a.first[s + 1]) ++s;  // wave-uniform
         const int inst = a.slot_inst[s];
-        const uint64_t chunk = idx - a.first[s];
+        const uint64_t item = idx - a.first[s];
         const BatchInstance& in = a.inst[inst];
         unsigned long long* t = tab + inst * kMaxPrimes * 2;
-        switch (in.kind) {
-#define SK_BATCH_CASE(KIND, V, N) \
-    case KIND:                    \
-        batch_case<V, N>(chunk, in, t); \
-        break;
-            SK_BATCH_CASES(SK_BATCH_CASE)
-#undef SK_BATCH_CASE
-            default:
-                break;
+        constexpr int lo = batch_group_lo(G);
+        switch (in.variant) {
+            case 0: dispatch_n<G, PPI, 0, lo>(in.n, item, in, t); break;
+            case 1: dispatch_n<G, PPI, 1, lo>(in.n, item, in, t); break;
+            case 2: dispatch_n<G, PPI, 2, lo>(in.n, item, in, t); break;
+            default: break;
         }
     }
     __syncthreads();  // every wave of the workgroup has left the loop
@@ -78,31 +112,12 @@ __global__ void __launch_bounds__(256) exact_batch_kernel(const BatchArgs a)
     }
 }
 
-}  // namespace sk
-
-namespace sk {
-
-hipError_t launch_exact_batch(unsigned blocks, hipStream_t stream, const BatchArgs& a)
+static hipError_t launch(unsigned blocks, hipStream_t stream, const BatchArgs& a)
 {
-    hipLaunchKernelGGL(exact_batch_kernel, dim3(blocks), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL((exact_batch_kernel<SK_BATCH_GROUP, SK_BATCH_PPI>), dim3(blocks), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
-// Clears n 64-bit words: accumulators and counters are cleared by a kernel on
-// the caller's stream rather than by a memset node, so a captured sequence of
-// calls replays the clearing too.
-__global__ void __launch_bounds__(256) zero_words_kernel(unsigned long long* __restrict__ p, uint64_t n)
-{
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
-}
-
-hipError_t launch_zero_words(void* p, uint64_t n, hipStream_t stream)
-{
-    if (n == 0) return hipSuccess;
-    const unsigned blocks = (unsigned)std::min<uint64_t>(64, (n + 255) / 256);
-    hipLaunchKernelGGL(zero_words_kernel, dim3(blocks), dim3(256), 0, stream, (unsigned long long*)p, n);
-    return hipGetLastError();
-}
+static const int registered = register_batch_kernel(SK_BATCH_GROUP, SK_BATCH_PPI, launch);
 
 }  // namespace sk

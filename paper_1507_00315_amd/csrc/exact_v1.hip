@@ -11,6 +11,8 @@
 // This body recomputes every pair sum from the sign mask at every step
 // (popcount form); it is the simple, obviously-correct kernel that the tuned
 // body (exact_v2.hip) is tested against.  The product path is shared.
+// With a.larsen it evaluates the inclusion-exclusion sum instead (0/1
+// variables, factors = occupied pairs at distance d_k; see exact_v2_body.h).
 #include <hip/hip_runtime.h>
 
 #include "exact_common.h"
@@ -29,7 +31,7 @@ __global__ void __launch_bounds__(256) exact_v1_kernel(const ExactArgs a, double
     if (active) {
         const uint64_t chunk = a.chunk_ids ? a.chunk_ids[wave] : a.chunk_base + wave;
 
-        uint64_t x_fixed = 0;
+        uint64_t x_fixed = a.x_extra;
         for (int b = 0; b < a.n_lane; ++b)
             if ((lane >> b) & 1) x_fixed |= 1ull << (a.var_pos[a.m - a.n_lane + b] - 1);
         const int cb = a.n_job - a.job_bits_per_chunk;
@@ -51,8 +53,12 @@ __global__ void __launch_bounds__(256) exact_v1_kernel(const ExactArgs a, double
                 int32_t f[4 * NQ];
 #pragma unroll
                 for (int s = 0; s < 4 * NQ; ++s) {
-                    const int c = __popcll((X ^ (X >> a.slot[s].d)) & a.slot[s].mask);
-                    f[s] = (a.slot[s].len - 2 * c) >> a.slot[s].halve;
+                    if (a.larsen) {  // occupied pairs at distance d_k; a constant-1 slot has no pairs
+                        f[s] = __popcll(X & (X >> a.slot[s].d) & a.slot[s].mask) + (a.slot[s].pad < 0 ? 1 : 0);
+                    } else {
+                        const int c = __popcll((X ^ (X >> a.slot[s].d)) & a.slot[s].mask);
+                        f[s] = (a.slot[s].len - 2 * c) >> a.slot[s].halve;
+                    }
                 }
                 double g[G];
                 group_products<NQ, G>(f, a.qb, g);
@@ -94,6 +100,23 @@ SK_V1_INST(5, 1) SK_V1_INST(5, 2) SK_V1_INST(5, 3) SK_V1_INST(5, 4)
 SK_V1_INST(6, 1) SK_V1_INST(6, 2) SK_V1_INST(6, 3) SK_V1_INST(6, 4)
 SK_V1_INST(7, 1) SK_V1_INST(7, 2) SK_V1_INST(7, 3) SK_V1_INST(7, 4)
 SK_V1_INST(8, 1) SK_V1_INST(8, 2) SK_V1_INST(8, 3) SK_V1_INST(8, 4)
+
+// Clears n 64-bit words: accumulators and counters are cleared by a kernel on
+// the caller's stream rather than by a memset node, so a captured sequence of
+// calls replays the clearing too.
+__global__ void __launch_bounds__(256) zero_words_kernel(unsigned long long* __restrict__ p, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+hipError_t launch_zero_words(void* p, uint64_t n, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)(n / 256 + 1 < 64 ? n / 256 + 1 : 64);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(blocks), dim3(256), 0, stream, (unsigned long long*)p, n);
+    return hipGetLastError();
+}
 
 using ExactKernelFn = void (*)(const ExactArgs, double*);
 

@@ -31,6 +31,14 @@
 //     one 24-bit multiply per quad reading both halves (SDWA), conversion to
 //     fp64, exact fp64 group products, then the fp64 residue chain of
 //     exact_common.h per prime.
+//
+// LARSEN = true evaluates the inclusion-exclusion sum of Sec. 2 (the third
+// counting approach) with the same machinery: the variables are y in {0, 1}
+// (1: position occupied, a set bit of the masks), the factors are
+// N_k(y) = sum_i y_i y_(i+d_k) >= 0 (nothing halved), a flip of y_q changes
+// N_k by +-(y_(q-d_k) + y_(q+d_k)), and the term's sign (-1)^(empty
+// positions) is the parity of the set bits, as for the sign sum (2n is
+// even).  Position 1 is not fixed: the host runs both of its values.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -77,9 +85,9 @@ __device__ __forceinline__ int32_t mul_halves(uint32_t x)
 
 constexpr uint32_t kHalfBias = 0x4000u;
 
-template <int V, int N, int P, int INNER>
+template <int V, int N, int P, int INNER, bool LARSEN = false>
 struct ExactV2 {
-    static constexpr PlanCE PL = make_plan_ce(N, V);
+    static constexpr PlanCE PL = make_plan_ce(N, V, kWalkCap, LARSEN);
     static_assert(PL.ok, "no plan");
     static constexpr int NS = 4 * PL.nq;  // slots
     static constexpr int NP = NS / 2;     // packed slot pairs
@@ -104,7 +112,9 @@ struct ExactV2 {
     static constexpr bool in_set(int p) { return p >= 1 && p <= 64 && ((PL.pset >> (p - 1)) & 1); }
     static constexpr int qpos(int b) { return 2 + b; }  // position of inner walked variable b
     static constexpr bool is_inner(int p) { return p >= 2 && p < 2 + INNER; }
-    static constexpr int g_of(int s) { return PL.slot_k[s] < 0 ? 0 : (PL.slot_halve[s] ? 1 : 2); }
+    // change of a pair term per unit neighbour value when one end flips:
+    // x_q x_r moves by 2 x_r (1 for a halved factor); y_q y_r by y_r
+    static constexpr int g_of(int s) { return PL.slot_k[s] < 0 ? 0 : (LARSEN || PL.slot_halve[s] ? 1 : 2); }
     static constexpr uint64_t lane_posmask()
     {
         uint64_t m = 0;
@@ -129,7 +139,11 @@ struct ExactV2 {
     }
     // inner state (bit b set <=> x = -1) at local step i of a block
     static constexpr int state(int i) { return (i ^ (i >> 1)) & ((1 << INNER) - 1); }
-    static constexpr int xval_state(int st, int b) { return ((st >> b) & 1) ? -1 : 1; }
+    // value of inner variable b in state st: x = -1 (bit set) or +1; y = bit
+    static constexpr int xval_state(int st, int b) { return LARSEN ? ((st >> b) & 1) : (((st >> b) & 1) ? -1 : 1); }
+    // whether the flip of inner variable b from state st raises the factors:
+    // x from -1 to +1, y from 0 to 1
+    static constexpr bool flip_raises(int st, int b) { return LARSEN ? !((st >> b) & 1) : ((st >> b) & 1); }
     static constexpr int ctz_ce(int i)
     {
         int c = 0;
@@ -166,7 +180,19 @@ struct ExactV2 {
         return -1;
     }
 
-    __device__ static __forceinline__ int xbit(uint64_t XU, int p) { return 1 - 2 * (int)((XU >> (p - 1)) & 1); }
+    // value of the variable at position p: x = +1 / -1 (bit clear / set), or y = bit
+    __device__ static __forceinline__ int xbit(uint64_t XU, int p)
+    {
+        if constexpr (LARSEN) return (int)((XU >> (p - 1)) & 1);
+        else return 1 - 2 * (int)((XU >> (p - 1)) & 1);
+    }
+    // pair terms of slot s on the edges `mask` of sign mask X: the sum of
+    // x_i x_(i+d) (L - 2 * disagreeing pairs) or of y_i y_(i+d)
+    __device__ static __forceinline__ int pair_sum(uint64_t X, uint64_t mask, int d)
+    {
+        if constexpr (LARSEN) return (int)__builtin_popcountll(X & (X >> d) & mask);
+        else return popc_ce(mask) - 2 * (int)__builtin_popcountll((X ^ (X >> d)) & mask);
+    }
 
     // Scalar state for a job: B (biased, integer-encoded pairs) and N_q.
     struct Uniform {
@@ -187,7 +213,7 @@ struct ExactV2 {
                 } else {
                     constexpr uint64_t mu = mask_unif(s);
                     constexpr int d = PL.slot_d[s];
-                    const int B = popc_ce(mu) - 2 * (int)__builtin_popcountll((u.XU ^ (u.XU >> d)) & mu);
+                    const int B = pair_sum(u.XU, mu, d);
                     if constexpr (PL.slot_halve[s]) {
                         constexpr int c = popc_ce(mu) & 1;
                         bh[decltype(hc)::value] = (B - c) >> 1;
@@ -223,6 +249,10 @@ struct ExactV2 {
     template <int R>
     __device__ static __forceinline__ void flip_outer(Uniform& u)
     {
+        // per unit neighbour value, the factors move by -x_r g (sign sum) or by
+        // +1 / -1 as y_r goes 0 -> 1 / 1 -> 0 (inclusion-exclusion); the sign
+        // sum keeps its own expressions (the same values; the compiler
+        // allocates registers better for them)
         const int xr = xbit(u.XU, R);  // value before the flip
         static_for<0, NP>([&](auto pc) {
             constexpr int p = decltype(pc)::value;
@@ -235,7 +265,8 @@ struct ExactV2 {
                     if constexpr (in_set(R - d)) sum += xbit(u.XU, R - d);
                     if constexpr (in_set(R + d)) sum += xbit(u.XU, R + d);
                 }
-                dh[decltype(hc)::value] = -xr * g_of(s) * sum;
+                if constexpr (LARSEN) dh[decltype(hc)::value] = (1 - 2 * xr) * sum;
+                else dh[decltype(hc)::value] = -xr * g_of(s) * sum;
             });
             u.B[p] += (uint32_t)(dh[0] + 65536 * dh[1]);
         });
@@ -244,7 +275,8 @@ struct ExactV2 {
             constexpr int s = slot_of_diff(R - qpos(b));
             if constexpr (s >= 0) {
                 constexpr int32_t unit = (s & 1) ? 65536 : 1;
-                u.Nq[b][s / 2] += -2 * xr * g_of(s) * unit;
+                if constexpr (LARSEN) u.Nq[b][s / 2] += (1 - 2 * xr) * unit;
+                else u.Nq[b][s / 2] += -2 * xr * g_of(s) * unit;
             }
         });
         u.XU ^= 1ull << (R - 1);
@@ -255,11 +287,11 @@ struct ExactV2 {
     __device__ static __forceinline__ void flip_inner(Uniform& u)
     {
         constexpr int b = ctz_ce(I);
-        constexpr int xb = xval_state(state(I - 1), b);  // before the flip
+        constexpr bool up = flip_raises(state(I - 1), b);
         static_for<0, NP>([&](auto pc) {
             constexpr int p = decltype(pc)::value;
             constexpr int32_t c = inner_const_pair(I, p);
-            if constexpr (xb < 0) {
+            if constexpr (up) {
                 u.B[p] += (uint32_t)u.Nq[b][p];
                 if constexpr (c != 0) u.B[p] += (uint32_t)c;
             } else {
@@ -341,12 +373,13 @@ struct ExactV2 {
 };
 
 // One chunk (chunk id, 2^jb jobs) evaluated by the calling wavefront.
+// x_extra: bits ORed into every job's mask (position 1's value for LARSEN).
 // Returns in every lane the wave's residues (balanced, exact fp64 integers).
-template <int V, int N, int P, int INNER>
+template <int V, int N, int P, int INNER, bool LARSEN = false>
 __device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const RevMasks& rev, const double (&pr)[P],
-                                               const double (&pinv)[P], double (&res)[P])
+                                               const double (&pinv)[P], double (&res)[P], uint64_t x_extra = 0)
 {
-    using K = ExactV2<V, N, P, INNER>;
+    using K = ExactV2<V, N, P, INNER, LARSEN>;
     constexpr PlanCE PL = K::PL;
     constexpr int NP = K::NP;
     constexpr int W = K::W;
@@ -368,7 +401,7 @@ __device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const Rev
     for (int i = 0; i < P; ++i) acc_tot[i] = 0.0;
 
     const uint64_t njobs = 1ull << jb;
-    const uint64_t xu_chunk = chunk << (1 + W + jb);
+    const uint64_t xu_chunk = (chunk << (1 + W + jb)) | x_extra;
     for (uint64_t j = 0; j < njobs; ++j) {
         const uint64_t xu_job = xu_chunk | (j << (1 + W));
         // reversal weight of this job (wave-uniform: job variables only)
@@ -398,7 +431,7 @@ __device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const Rev
                 } else {
                     constexpr uint64_t ml = K::mask_lane(s);
                     constexpr int d = PL.slot_d[s];
-                    const int Av = K::popc_ce(ml) - 2 * (int)__builtin_popcountll((X ^ (X >> d)) & ml);
+                    const int Av = K::pair_sum(X, ml, d);
                     if constexpr (PL.slot_halve[s]) {
                         constexpr int c = K::popc_ce(K::mask_unif(s)) & 1;
                         ah[decltype(hc)::value] = (Av + c) >> 1;
@@ -462,7 +495,7 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
            (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
 }
 
-template <int V, int N, int P, int INNER>
+template <int V, int N, int P, int INNER, bool LARSEN = false>
 __global__ void __launch_bounds__(256) exact_v2_kernel(const ExactArgsV2 a, double* __restrict__ out)
 {
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -476,7 +509,7 @@ __global__ void __launch_bounds__(256) exact_v2_kernel(const ExactArgsV2 a, doub
     }
     if (active) {
         const uint64_t chunk = uniform_u64(a.chunk_ids ? a.chunk_ids[wave] : a.chunk_base + wave);
-        exact_v2_chunk<V, N, P, INNER>(chunk, a.job_bits_per_chunk, a.rev, pr, pinv, res);
+        exact_v2_chunk<V, N, P, INNER, LARSEN>(chunk, a.job_bits_per_chunk, a.rev, pr, pinv, res, a.x_extra);
         if ((threadIdx.x & 63) == 0 && !a.acc) {
 #pragma unroll
             for (int i = 0; i < P; ++i) out[wave * P + i] = res[i];

@@ -183,6 +183,7 @@ struct Plan {
     int halved = 0;          // number of factors stored as f_k / 2
     SlotDesc slot[kMaxSlots];
     bool zero_factor = false;  // some f_k is identically 0 (no pairs at that distance)
+    bool larsen = false;       // plan of the inclusion-exclusion sum (nothing halved)
 };
 
 static bool existence(int n, int v)
@@ -243,11 +244,12 @@ static uint64_t reversal_evaluated(uint64_t total, int r)
     return r == 0 ? total : (total >> (r + 1)) * ((1ull << r) + 1);
 }
 
-static sk_status make_plan(int n, int variant, Plan& P)
+static sk_status make_plan(int n, int variant, Plan& P, bool larsen = false)
 {
     if (variant < 0 || variant > 2) return SK_EINVAL;
     if (n < 1 || n > kMaxN || (variant == SK_HOOKED && n > kMaxN - 1)) return SK_EINVAL;
-    const PlanCE C = make_plan_ce(n, variant);
+    const PlanCE C = make_plan_ce(n, variant, kWalkCap, larsen);
+    P.larsen = larsen;
     if (!C.ok) return SK_ENOLIB;
     P.n = C.n;
     P.variant = C.variant;
@@ -283,12 +285,16 @@ struct DeviceCtx {
 };
 
 static DeviceCtx g_ctx[64];
+static std::mutex g_ctx_mu;
 
+// Per-device set-up, once per device with that device current: the library's
+// stream and the CU count.
 static sk_status device_ctx(DeviceCtx** out)
 {
     if (g_device < 0 || g_device >= 64) return SK_EINVAL;
     DeviceCtx& c = g_ctx[g_device];
     SK_HIP(hipSetDevice(g_device));
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
     if (!c.ready) {
         hipDeviceProp_t prop;
         SK_HIP(hipGetDeviceProperties(&prop, g_device));
@@ -363,16 +369,16 @@ struct V2Entry {
     int inner = 0;
 };
 
-static V2Entry& v2_slot(int variant, int n)
+static V2Entry& v2_slot(int variant, int n, bool larsen = false)
 {
-    static V2Entry table[3][kMaxN + 1];
-    return table[variant][n];
+    static V2Entry table[2][3][kMaxN + 1];
+    return table[larsen ? 1 : 0][variant][n];
 }
 
-int register_exact_v2(int variant, int n, int nprimes, int inner, ExactV2Fn fn)
+int register_exact_v2(int variant, int n, int nprimes, int inner, bool larsen, ExactV2Fn fn)
 {
     if (variant < 0 || variant > 2 || n < 1 || n > kMaxN) return 0;
-    V2Entry& e = v2_slot(variant, n);
+    V2Entry& e = v2_slot(variant, n, larsen);
     e.fn = fn;
     e.nprimes = nprimes;
     e.inner = inner;
@@ -384,7 +390,7 @@ int register_exact_v2(int variant, int n, int nprimes, int inner, ExactV2Fn fn)
 static int pick_kernel(const Plan& P, int requested)
 {
     if (requested == 1) return 1;
-    if (v2_slot(P.variant, P.n).fn) return 2;
+    if (v2_slot(P.variant, P.n, P.larsen).fn) return 2;
     return requested == 2 ? -1 : 1;
 }
 
@@ -405,8 +411,8 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
     ExactV2Fn fn2 = nullptr;
     int batch = 0;  // primes per launch
     if (kv == 2) {
-        fn2 = v2_slot(P.variant, P.n).fn;
-        batch = v2_slot(P.variant, P.n).nprimes;
+        fn2 = v2_slot(P.variant, P.n, P.larsen).fn;
+        batch = v2_slot(P.variant, P.n, P.larsen).nprimes;
     } else {
         fn1 = exact_v1_lookup(P.nq, P.G);
         if (!fn1) return SK_ENOLIB;
@@ -414,6 +420,9 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
     }
 
     const bool listed = R.chunk_ids != nullptr;
+    if (P.larsen && (listed || R.half || R.reverse)) return SK_EINVAL;
+    // the inclusion-exclusion sum leaves position 1 free: both of its values
+    const int x0_passes = P.larsen ? 2 : 1;
     int jb;
     uint64_t nchunks;
     if (listed) {
@@ -449,7 +458,7 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
     const int rev_r = rev.r;
     const uint64_t terms_per_chunk = 1ull << (P.n_lane + P.n_walk + jb);
     const int nbatches = (np + batch - 1) / batch;
-    const uint64_t terms_total = nchunks * terms_per_chunk * (uint64_t)nbatches;
+    const uint64_t terms_total = nchunks * terms_per_chunk * (uint64_t)nbatches * x0_passes;
 
     DeviceCtx* ctx;
     sk_status stt = device_ctx(&ctx);
@@ -499,7 +508,9 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
     if (listed) out.assign(nchunks * np, 0);
     else out.assign(np, 0);
 
-    for (int bt = 0; bt < nbatches; ++bt) {
+    for (int pass = 0; pass < nbatches * x0_passes; ++pass) {
+        const int bt = pass % nbatches;
+        const uint64_t x_extra = pass / nbatches;  // position 1 (bit 0) occupied in the second pass
         // primes of this launch batch; the last batch repeats its last prime
         std::vector<uint64_t> bp(batch);
         for (int i = 0; i < batch; ++i) bp[i] = R.primes[std::min(np - 1, bt * batch + i)];
@@ -526,6 +537,8 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
             for (int g = 0; g < 5; ++g) a1.qb[g] = P.qb[g];
             a1.job_bits_per_chunk = jb;
             a1.acc = acc;
+            a1.larsen = P.larsen ? 1 : 0;
+            a1.x_extra = x_extra;
         } else {
             for (int i = 0; i < batch; ++i) {
                 a2.prime[i] = (double)bp[i];
@@ -534,6 +547,7 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
             a2.job_bits_per_chunk = jb;
             if (rev_r > 0) a2.rev = rev;
             a2.acc = acc;
+            a2.x_extra = x_extra;
         }
         for (uint64_t base = 0; base < nchunks; base += wpl) {
             const uint64_t nw = std::min<uint64_t>(wpl, nchunks - base);
@@ -595,7 +609,7 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
     }
     if (!R.timing)
         st.kernel_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_host).count();
-    st.terms += reversal_evaluated(nchunks * terms_per_chunk, rev_r);
+    st.terms += reversal_evaluated(nchunks * terms_per_chunk, rev_r) * x0_passes;
     st.reversal_quads = rev_r;
     st.chunks += nchunks;
     st.log2_chunk_terms = P.n_lane + P.n_walk + jb;
@@ -651,20 +665,26 @@ namespace sk {
 
 // ------------------------------------------------------------------ batch
 
-hipError_t launch_exact_batch(unsigned blocks, hipStream_t stream, const BatchArgs& a);
-
 // Device workspace of the counting entry points (sk_count_ex, sk_count_part,
 // sk_count_batch): one batched launch's accumulators and counter, which also
 // hold the accumulators of a separate count.
 constexpr size_t kCountWsBytes = kBatchWsBytes > kSumAccBytes ? kBatchWsBytes : kSumAccBytes;
 
-static int batch_kind(int variant, int n)
+static BatchLaunchFn g_batch_fn[kBatchGroups][2];
+
+int register_batch_kernel(int group, int ppi, BatchLaunchFn fn)
 {
-#define SK_BATCH_KIND(KIND, V, N) \
-    if (variant == V && n == N) return KIND;
-    SK_BATCH_CASES(SK_BATCH_KIND)
-#undef SK_BATCH_KIND
-    return -1;
+    if (group < 0 || group >= kBatchGroups || ppi < 0 || ppi > 1) return 0;
+    g_batch_fn[group][ppi] = fn;
+    return 1;
+}
+
+// Group whose batched kernel holds the tuned body of (variant, n), or -1.
+static int batch_group(int variant, int n)
+{
+    const int g = batch_group_of(variant, n);
+    if (g < 0 || !g_batch_fn[g][0] || !v2_slot(variant, n).fn) return -1;
+    return g;
 }
 
 struct BatchJob {
@@ -679,12 +699,15 @@ struct BatchJob {
 // One persistent launch over the chunks of every job.  probe_shift > 0 runs
 // only the first 2^-probe_shift of each job's chunks (used by the autotuner).
 // ws: device workspace of at least kBatchWsBytes (nullptr: allocated here).
-static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t waves, hipStream_t stream,
-                           int probe_shift, sk_stats& st, double* kernel_ms, void* ws_in = nullptr,
-                           bool timing = true)
+static sk_status run_batch(std::vector<BatchJob>& jobs, int group, int log2_chunk, uint64_t waves, int ppi,
+                           hipStream_t stream, int probe_shift, sk_stats& st, double* kernel_ms,
+                           void* ws_in = nullptr, bool timing = true)
 {
     if (jobs.empty()) return SK_OK;
-    if ((int)jobs.size() > kBatchMaxInstances) return SK_EINVAL;
+    if ((int)jobs.size() > kBatchMaxInstances || group < 0 || group >= kBatchGroups || ppi < 0 || ppi > 1)
+        return SK_EINVAL;
+    const BatchLaunchFn launch = g_batch_fn[group][ppi];
+    if (!launch) return SK_ENOLIB;
     DeviceCtx* ctx;
     sk_status s = device_ctx(&ctx);
     if (s != SK_OK) return s;
@@ -698,11 +721,12 @@ static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t
     std::vector<uint64_t> nch(jobs.size());
     for (size_t b = 0; b < jobs.size(); ++b) {
         const Plan& P = *jobs[b].plan;
-        const int kind = batch_kind(P.variant, P.n);
-        if (kind < 0 || (int)jobs[b].primes.size() != primes_for(P.n)) return SK_ENOLIB;
+        if (batch_group(P.variant, P.n) != group || (int)jobs[b].primes.size() != primes_for(P.n)) return SK_ENOLIB;
         int jb = log2_chunk - P.n_lane - P.n_walk;
         jb = std::max(0, std::min(jb, P.n_job));
-        a.inst[b].kind = kind;
+        a.inst[b].variant = P.variant;
+        a.inst[b].n = P.n;
+        a.inst[b].nprimes = (int32_t)jobs[b].primes.size();
         a.inst[b].jb = jb;
         if (jobs[b].reverse) a.inst[b].rev = reversal_masks(P);
         for (size_t i = 0; i < jobs[b].primes.size(); ++i) {
@@ -724,7 +748,8 @@ static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t
     for (size_t k = 0; k < order.size(); ++k) {
         a.first[k] = (uint32_t)n_items;
         a.slot_inst[k] = (int32_t)order[k];
-        n_items += nch[order[k]];
+        // one prime per item: each chunk is P items
+        n_items += nch[order[k]] * (ppi == 1 ? jobs[order[k]].primes.size() : 1);
         if (n_items >= (1ull << 32)) return SK_EINVAL;
     }
     a.first[order.size()] = (uint32_t)n_items;
@@ -756,7 +781,7 @@ static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t
     // accumulators and counter: one 8-byte word per accumulator half, one for the counter
     if ((e = launch_zero_words(ws, kBatchAccBytes / 8 + 1, stream)) != hipSuccess) { fail(e, "zero workspace"); goto done; }
     if (e0 && (e = hipEventRecord(e0, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
-    if ((e = launch_exact_batch(blocks, stream, a)) != hipSuccess) { fail(e, "batch launch"); goto done; }
+    if ((e = launch(blocks, stream, a)) != hipSuccess) { fail(e, "batch launch"); goto done; }
     if (e1 && (e = hipEventRecord(e1, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
     if ((e = hipMemcpyAsync(h_acc.data(), a.acc, kBatchAccBytes, hipMemcpyDeviceToHost, stream)) != hipSuccess) {
         fail(e, "hipMemcpyAsync");
@@ -783,7 +808,8 @@ static sk_status run_batch(std::vector<BatchJob>& jobs, int log2_chunk, uint64_t
     st.kernel_ms += ms;
     st.launches += 1;
     st.chunks += n_items;
-    for (auto& j : jobs) st.terms += j.terms;
+    // sign vectors evaluated: every one once per item that holds it
+    for (auto& j : jobs) st.terms += j.terms * (ppi == 1 ? j.primes.size() : 1);
     st.log2_chunk_terms = log2_chunk;
     st.kernel_variant = 3;
     for (auto& j : jobs)
@@ -795,10 +821,16 @@ done:
     return status;
 }
 
-// ----- autotune cache: (arch, CUs, instance list) -> (log2_chunk, waves)
+// ----- autotune cache: (arch, CUs, instance list) -> launch shape
+
+struct BatchShape {
+    int log2_chunk = 27;
+    uint64_t waves = 0;
+    int ppi = 0;  // primes per work item: 0 all, 1 one
+};
 
 static std::mutex g_tune_mu;
-static std::map<std::string, std::pair<int, uint64_t>> g_tune;
+static std::map<std::string, BatchShape> g_tune;
 static bool g_tune_loaded = false;
 
 static std::string tune_path()
@@ -809,6 +841,8 @@ static std::string tune_path()
     return std::string(h ? h : "/tmp") + "/.cache/skolem_mi355x_tune.txt";
 }
 
+// One line per instance set: key, log2 sign vectors per item, waves, and
+// (optionally) primes per item.
 static void tune_load()
 {
     if (g_tune_loaded) return;
@@ -818,9 +852,11 @@ static void tune_load()
     while (std::getline(f, line)) {
         std::istringstream is(line);
         std::string key;
-        int lc;
-        uint64_t w;
-        if (is >> key >> lc >> w) g_tune[key] = {lc, w};
+        BatchShape b;
+        if (is >> key >> b.log2_chunk >> b.waves) {
+            if (!(is >> b.ppi) || b.ppi < 0 || b.ppi > 1) b.ppi = 0;
+            g_tune[key] = b;
+        }
     }
 }
 
@@ -830,8 +866,7 @@ static void tune_store()
     const size_t slash = path.find_last_of('/');
     if (slash != std::string::npos) {
         std::string dir = path.substr(0, slash);
-        std::string cmd;  // create the directory without a shell
-        for (size_t i = 1; i <= dir.size(); ++i) {
+        for (size_t i = 1; i <= dir.size(); ++i) {  // create the directory without a shell
             if (i == dir.size() || dir[i] == '/') {
                 std::string sub = dir.substr(0, i);
                 (void)::mkdir(sub.c_str(), 0755);
@@ -839,7 +874,8 @@ static void tune_store()
         }
     }
     std::ofstream f(path, std::ios::trunc);
-    for (auto& kv : g_tune) f << kv.first << " " << kv.second.first << " " << kv.second.second << "\n";
+    for (auto& kv : g_tune)
+        f << kv.first << " " << kv.second.log2_chunk << " " << kv.second.waves << " " << kv.second.ppi << "\n";
 }
 
 static std::string tune_key(const std::vector<const Plan*>& plans)
@@ -862,44 +898,57 @@ static std::string tune_key(const std::vector<const Plan*>& plans)
     return os.str();
 }
 
-// Times the batch on 1/16 of every instance for each candidate shape and
-// keeps the fastest (sign vectors per second).  Candidates: 2^22 .. 2^28 sign
-// vectors per work item and 2 .. 8 persistent waves per SIMD.  Smaller work
-// items balance the tail of the launch better, but below 2^22 the host's
-// share (the work list and one residue row per item) outweighs the gain.
-static sk_status autotune(const std::vector<const Plan*>& plans, hipStream_t stream, int* best_lc,
-                          uint64_t* best_w, double* best_rate)
+// Times the batched launch of one group's instances on a fraction of every
+// instance's chunks (about 2^36 sign vectors in all, at most 1/16) for each
+// candidate shape and keeps the fastest in sign vectors of the count per
+// second.  Candidates: 2^22 .. 2^28 sign vectors per work item, 2 .. 8
+// persistent waves per SIMD, and where the group has a kernel for it one prime
+// per work item instead of all of them.  Smaller work items balance the tail of
+// the launch better; one prime per item repeats the pair sums and products
+// for every prime.
+static sk_status autotune(const std::vector<const Plan*>& plans, int group, hipStream_t stream, BatchShape* best_out,
+                          double* best_rate)
 {
     DeviceCtx* ctx;
     sk_status s = device_ctx(&ctx);
     if (s != SK_OK) return s;
+    uint64_t total = 0;
+    for (auto* p : plans) total += 1ull << (p->m - 1 - (hat_symmetric(*p) ? 1 : 0));
+    int shift = 4;
+    while (shift < 20 && (total >> shift) > (1ull << 36)) ++shift;
     const int lcs[] = {22, 24, 26, 28};
     const int wps[] = {2, 4, 6, 8};
     double best = -1.0;
-    for (int lc : lcs) {
-        for (int wp : wps) {
-            std::vector<BatchJob> jobs;
-            for (auto* p : plans) {
-                // the same work per item as the production batch: Lemma 2.4
-                // half and reversal weights (weight-0 jobs skipped in a chunk)
-                BatchJob j;
-                j.plan = p;
-                j.primes = default_primes(primes_for(p->n), 0);
-                j.half = hat_symmetric(*p);
-                j.reverse = true;
-                jobs.push_back(j);
-            }
-            sk_stats st;
-            std::memset(&st, 0, sizeof(st));
-            double ms = 0;
-            const uint64_t waves = (uint64_t)ctx->cus * 4 * wp;
-            s = run_batch(jobs, lc, waves, stream, 4, st, &ms);
-            if (s != SK_OK) return s;
-            const double rate = (double)st.terms / (ms * 1e-3);
-            if (rate > best) {
-                best = rate;
-                *best_lc = lc;
-                *best_w = waves;
+    for (int ppi = 0; ppi <= 1; ++ppi) {
+        if (!g_batch_fn[group][ppi]) continue;
+        for (int lc : lcs) {
+            for (int wp : wps) {
+                std::vector<BatchJob> jobs;
+                for (auto* p : plans) {
+                    // the same work per item as the production batch: Lemma 2.4
+                    // half and reversal weights (weight-0 jobs skipped in a chunk)
+                    BatchJob j;
+                    j.plan = p;
+                    j.primes = default_primes(primes_for(p->n), 0);
+                    j.half = hat_symmetric(*p);
+                    j.reverse = true;
+                    jobs.push_back(j);
+                }
+                sk_stats st;
+                std::memset(&st, 0, sizeof(st));
+                double ms = 0;
+                const uint64_t waves = (uint64_t)ctx->cus * 4 * wp;
+                s = run_batch(jobs, group, lc, waves, ppi, stream, shift, st, &ms);
+                if (s != SK_OK) return s;
+                uint64_t covered = 0;
+                for (auto& j : jobs) covered += j.terms;
+                const double rate = (double)covered / (ms * 1e-3);
+                if (rate > best) {
+                    best = rate;
+                    best_out->log2_chunk = lc;
+                    best_out->waves = waves;
+                    best_out->ppi = ppi;
+                }
             }
         }
     }
@@ -961,6 +1010,63 @@ static sk_status count_impl(int n, int variant, unsigned flags, const sk_tuning*
             Big c;
             s = residues_to_count(P, R.primes, res, c);
             if (s != SK_OK) return s;
+            if (pass == 0) first = c;
+            else if (c.cmp(first) != 0) {
+                g_last_error = "verification pass with disjoint primes disagrees";
+                return SK_ECHECK;
+            }
+            for (int i = 0; i < np; ++i) st.primes[pass * np + i] = R.primes[i];
+        }
+        st.nprimes = np;
+        st.passes = passes;
+        result = ((u128)first.w[1] << 64) | first.w[0];
+    }
+    s = halve_reported(n, variant, flags, result);
+    if (s != SK_OK) return s;
+    out->lo = (uint64_t)result;
+    out->hi = (uint64_t)(result >> 64);
+    st.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    st.ms_per_launch_avg = st.launches ? st.kernel_ms / (double)st.launches : 0.0;
+    g_stats = st;
+    if (stats_out) *stats_out = st;
+    return SK_OK;
+}
+
+sk_status sk_count_larsen(int n, int variant, unsigned flags, const sk_tuning* tune, void* dev_workspace,
+                          size_t ws_bytes, void* stream, sk_stats* stats_out, sk_u128* out)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!out) return SK_EINVAL;
+    Plan P;
+    sk_status s = make_plan(n, variant, P, true);
+    if (s != SK_OK) return s;
+    sk_stats st;
+    std::memset(&st, 0, sizeof(st));
+    u128 result = 0;
+    if (existence(n, variant) || (flags & SK_NO_SHORTCUT)) {
+        const int np = (tune && tune->primes > 0) ? std::max(primes_needed(n), std::min(tune->primes, kMaxPrimes))
+                                                  : primes_needed(n);
+        const int passes = (flags & SK_VERIFY) ? 2 : 1;
+        Big first;
+        for (int pass = 0; pass < passes; ++pass) {
+            SumRequest R;
+            R.plan = &P;
+            R.primes = default_primes(np, pass * np);
+            R.log2_chunk_terms = (tune && tune->log2_chunk_terms > 0) ? tune->log2_chunk_terms : 0;
+            R.waves_per_launch = tune ? tune->waves_per_launch : 0;
+            R.kernel = tune ? tune->kernel : 0;
+            R.stream = (hipStream_t)stream;
+            R.ws = dev_workspace;
+            R.ws_bytes = ws_bytes;
+            std::vector<uint64_t> res;
+            s = run_sum(R, res, st);
+            if (s != SK_OK) return s;
+            // the sum is the ordered count itself: no power of two to divide out
+            Big c = crt(res, R.primes);
+            if (c.cmp(factorial_big(P.n)) > 0 || !c.fits128()) {
+                g_last_error = "CRT result exceeds the bound n!";
+                return SK_ECHECK;
+            }
             if (pass == 0) first = c;
             else if (c.cmp(first) != 0) {
                 g_last_error = "verification pass with disjoint primes disagrees";
@@ -1092,47 +1198,47 @@ static sk_status batch_impl(const sk_instance* inst, size_t k, const sk_tuning* 
     sk_stats st;
     std::memset(&st, 0, sizeof(st));
     std::vector<u128> result(k, 0);
-    std::vector<int> batched, separate;
+    // instances of each batched group, and those counted by separate launches
+    std::vector<std::vector<int>> batched(kBatchGroups);
+    std::vector<int> separate;
     for (size_t i = 0; i < k; ++i) {
         const bool needed = existence(inst[i].n, inst[i].variant) || (inst[i].flags & SK_NO_SHORTCUT);
         if (!needed) continue;
-        const bool can = batch_kind(inst[i].variant, inst[i].n) >= 0 && v2_slot(inst[i].variant, inst[i].n).fn &&
-                         !(tune && (tune->kernel == 1 || tune->primes > primes_for(inst[i].n)));
-        (can ? batched : separate).push_back((int)i);
+        const int g = batch_group(inst[i].variant, inst[i].n);
+        const bool can = g >= 0 && !(tune && (tune->kernel == 1 || tune->primes > primes_for(inst[i].n)));
+        if (can && (int)batched[g].size() < kBatchMaxInstances) batched[g].push_back((int)i);
+        else separate.push_back((int)i);
     }
-    if ((int)batched.size() > kBatchMaxInstances) {
-        separate.insert(separate.end(), batched.begin() + kBatchMaxInstances, batched.end());
-        batched.resize(kBatchMaxInstances);
-    }
-    if (!batched.empty()) {
-        std::vector<const Plan*> bp;
-        for (int i : batched) bp.push_back(&plans[i]);
-        int lc = 27;
-        uint64_t waves = 0;
-        DeviceCtx* ctx;
+    DeviceCtx* ctx;
+    {
         sk_status s = device_ctx(&ctx);
         if (s != SK_OK) return s;
-        waves = (uint64_t)ctx->cus * 4 * 2;
+    }
+    for (int g = 0; g < kBatchGroups; ++g) {
+        if (batched[g].empty()) continue;
+        std::vector<const Plan*> bp;
+        for (int i : batched[g]) bp.push_back(&plans[i]);
+        BatchShape shape;
+        shape.waves = (uint64_t)ctx->cus * 4 * 2;
         if (tune && tune->log2_chunk_terms > 0) {
-            lc = tune->log2_chunk_terms;
-            if (tune->waves_per_launch > 0) waves = (uint64_t)tune->waves_per_launch;
+            shape.log2_chunk = tune->log2_chunk_terms;
+            if (tune->waves_per_launch > 0) shape.waves = (uint64_t)tune->waves_per_launch;
+            shape.ppi = tune->primes_per_item == 1 ? 1 : 0;
         } else {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             tune_load();
             auto it = g_tune.find(tune_key(bp));
-            if (it != g_tune.end()) {
-                lc = it->second.first;
-                waves = it->second.second;
-            }
+            if (it != g_tune.end()) shape = it->second;
         }
+        if (shape.ppi == 1 && !g_batch_fn[g][1]) shape.ppi = 0;
         int passes = 1;
-        for (int i : batched)
+        for (int i : batched[g])
             if (inst[i].flags & SK_VERIFY) passes = 2;
         std::vector<Big> first(k);
         for (int pass = 0; pass < passes; ++pass) {
             std::vector<BatchJob> jobs;
             std::vector<int> who;
-            for (int i : batched) {
+            for (int i : batched[g]) {
                 if (pass == 1 && !(inst[i].flags & SK_VERIFY)) continue;
                 BatchJob j;
                 j.plan = &plans[i];
@@ -1143,7 +1249,8 @@ static sk_status batch_impl(const sk_instance* inst, size_t k, const sk_tuning* 
                 jobs.push_back(j);
                 who.push_back(i);
             }
-            s = run_batch(jobs, lc, waves, (hipStream_t)stream, 0, st, nullptr, ws, timing);
+            sk_status s = run_batch(jobs, g, shape.log2_chunk, shape.waves, shape.ppi, (hipStream_t)stream, 0, st,
+                                    nullptr, ws, timing);
             if (s != SK_OK) return s;
             for (size_t b = 0; b < jobs.size(); ++b) {
                 const int i = who[b];
@@ -1159,7 +1266,7 @@ static sk_status batch_impl(const sk_instance* inst, size_t k, const sk_tuning* 
                 }
             }
         }
-        st.passes = passes;
+        st.passes = std::max(st.passes, passes);
     }
     for (int i : separate) {
         sk_stats s1;
@@ -1221,27 +1328,44 @@ sk_status sk_autotune_batch(const sk_instance* inst, size_t k, void* stream, sk_
 {
     if (!inst || k == 0 || !best) return SK_EINVAL;
     std::vector<Plan> plans(k);
-    std::vector<const Plan*> bp;
+    std::vector<std::vector<const Plan*>> groups(kBatchGroups);
     for (size_t i = 0; i < k; ++i) {
         sk_status s = make_plan(inst[i].n, inst[i].variant, plans[i]);
         if (s != SK_OK) return s;
-        if (batch_kind(inst[i].variant, inst[i].n) < 0 || !v2_slot(inst[i].variant, inst[i].n).fn) return SK_ENOLIB;
-        bp.push_back(&plans[i]);
+        const int g = batch_group(inst[i].variant, inst[i].n);
+        if (g < 0) return SK_ENOLIB;
+        groups[g].push_back(&plans[i]);
     }
-    if (bp.size() > (size_t)kBatchMaxInstances) return SK_EINVAL;
-    int lc = 0;
-    uint64_t w = 0;
-    sk_status s = autotune(bp, (hipStream_t)stream, &lc, &w, best_rate);
-    if (s != SK_OK) return s;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_load();
-        g_tune[tune_key(bp)] = {lc, w};
-        tune_store();
+    // every group is tuned and cached; the shape returned is that of the group
+    // with the most sign vectors
+    BatchShape out;
+    double out_rate = 0, most = -1;
+    for (int g = 0; g < kBatchGroups; ++g) {
+        if (groups[g].empty()) continue;
+        if (groups[g].size() > (size_t)kBatchMaxInstances) return SK_EINVAL;
+        BatchShape shape;
+        double rate = 0;
+        sk_status s = autotune(groups[g], g, (hipStream_t)stream, &shape, &rate);
+        if (s != SK_OK) return s;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            tune_load();
+            g_tune[tune_key(groups[g])] = shape;
+            tune_store();
+        }
+        double work = 0;
+        for (auto* p : groups[g]) work += std::ldexp(1.0, p->m - 1);
+        if (work > most) {
+            most = work;
+            out = shape;
+            out_rate = rate;
+        }
     }
+    if (best_rate) *best_rate = out_rate;
     std::memset(best, 0, sizeof(*best));
-    best->log2_chunk_terms = lc;
-    best->waves_per_launch = (int)w;
+    best->log2_chunk_terms = out.log2_chunk;
+    best->waves_per_launch = (int)out.waves;
+    best->primes_per_item = out.ppi;
     return SK_OK;
 }
 
@@ -1276,11 +1400,11 @@ int sk_max_chunk_bits(int n, int variant)
     return P.n_job;
 }
 
-sk_status sk_describe(int n, int variant, sk_plan_desc* out)
+static sk_status describe_impl(int n, int variant, bool larsen, sk_plan_desc* out)
 {
     if (!out) return SK_EINVAL;
     Plan P;
-    sk_status s = make_plan(n, variant, P);
+    sk_status s = make_plan(n, variant, P, larsen);
     if (s != SK_OK) return s;
     out->m = P.m;
     out->n_lane = P.n_lane;
@@ -1291,10 +1415,14 @@ sk_status sk_describe(int n, int variant, sk_plan_desc* out)
     out->halved = P.halved;
     out->primes = primes_needed(n);
     for (int i = 0; i < 32; ++i) out->slot_factor[i] = (i < 4 * P.nq) ? P.slot[i].pad : -1;
-    out->symmetric = hat_symmetric(P) ? 1 : 0;
-    out->reversal_quads = reversal_masks(P).r;
+    out->symmetric = larsen ? 0 : (hat_symmetric(P) ? 1 : 0);
+    out->reversal_quads = larsen ? 0 : reversal_masks(P).r;
     return SK_OK;
 }
+
+sk_status sk_describe(int n, int variant, sk_plan_desc* out) { return describe_impl(n, variant, false, out); }
+
+sk_status sk_describe_larsen(int n, int variant, sk_plan_desc* out) { return describe_impl(n, variant, true, out); }
 
 sk_status sk_partial_chunks(int n, int variant, int log2_chunks, const uint64_t* chunk_ids, size_t nchunks,
                             const uint64_t* primes, int nprimes, const sk_tuning* tune, void* dev_workspace,

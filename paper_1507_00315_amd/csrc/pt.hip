@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
             occ[s[k] + d]++;
         }
         for (int p = 1; p <= top; ++p)
-            if (((a.pset >> (p - 1)) & 1) && occ[p] == 0) ++E;
+            if (!(V == 2 && p == 2 * n) && occ[p] == 0) ++E;  // the hooked set has no position 2n
     }
     __syncthreads();
 

@@ -30,26 +30,27 @@ static uint32_t accept_threshold(double b, int e)
 
 struct Relaxed {
     int n = 0, variant = 0, top = 0, m = 0;
-    uint64_t pset = 0;
-    std::vector<int> L;  // placements of each pair
+    std::vector<char> in_set;  // in_set[p]: position p belongs to P (p = 0..top)
+    std::vector<int> L;        // placements of each pair
 };
 
 static bool relaxed_of(int n, int variant, Relaxed& R)
 {
-    if (n < 1 || n > 32 || variant < 0 || variant > 2 || (variant == 2 && n > 31)) return false;
+    if (n < 1 || n > kPtMaxN || variant < 0 || variant > 2) return false;
     R.n = n;
     R.variant = variant;
     R.top = variant == 2 ? 2 * n + 1 : 2 * n;
+    R.in_set.assign(R.top + 1, 0);
     for (int p = 1; p <= R.top; ++p) {
         if (variant == 2 && p == 2 * n) continue;
-        R.pset |= 1ull << (p - 1);
+        R.in_set[p] = 1;
         ++R.m;
     }
     for (int k = 0; k < n; ++k) {
         const int d = variant == 1 ? k + 2 : k + 1;
         int c = 0;
         for (int a = 1; a + d <= R.top; ++a)
-            if (((R.pset >> (a - 1)) & 1) && ((R.pset >> (a + d - 1)) & 1)) ++c;
+            if (R.in_set[a] && R.in_set[a + d]) ++c;
         R.L.push_back(c);
     }
     return true;
@@ -75,6 +76,9 @@ struct PtExtra {
     double gpu_ms = 0, train_ms = 0, train_loss = 0;
     uint64_t learned_moves = 0;
     std::vector<uint64_t> learned_acc;  // ladders x levels
+    bool want_half = false;             // record the histograms of the first part of the run
+    std::vector<uint64_t> hist_first;   // ladders x levels x bins, recorded iterations [0, first_iters)
+    uint64_t first_iters = 0;
 };
 
 // Device state of one run: thresholds, the two configuration buffers the
@@ -83,7 +87,7 @@ struct PtDevice {
     uint32_t *mt = nullptr, *st = nullptr;
     uint8_t *sa = nullptr, *sb = nullptr;
     int32_t* e = nullptr;
-    uint64_t *h = nullptr, *ma = nullptr, *sw = nullptr, *la = nullptr;
+    uint64_t *h = nullptr, *ma = nullptr, *sw = nullptr, *la = nullptr, *h1 = nullptr;
     float* beta_f = nullptr;
     uint8_t *pool = nullptr;
     float* pool_beta = nullptr;
@@ -94,7 +98,7 @@ struct PtDevice {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         for (void* p : {(void*)mt, (void*)st, (void*)sa, (void*)sb, (void*)e, (void*)h, (void*)ma, (void*)sw,
-                        (void*)la, (void*)beta_f, (void*)pool, (void*)pool_beta})
+                        (void*)la, (void*)beta_f, (void*)pool, (void*)pool_beta, (void*)h1})
             if (p) (void)hipFree(p);
     }
 };
@@ -190,6 +194,7 @@ static sk_status pt_run_impl(const Relaxed& R, const sk_pt_params* p, hipStream_
     PT_HIP(hipMalloc(&D.h, nh * sizeof(uint64_t)));
     PT_HIP(hipMalloc(&D.ma, nl * sizeof(uint64_t)));
     PT_HIP(hipMalloc(&D.sw, nl * sizeof(uint64_t)));
+    if (ex && ex->want_half) PT_HIP(hipMalloc(&D.h1, nh * sizeof(uint64_t)));
     PT_HIP(hipEventCreate(&D.e0));
     PT_HIP(hipEventCreate(&D.e1));
     PT_HIP(hipMemcpyAsync(D.mt, mt.data(), mt.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
@@ -201,7 +206,6 @@ static sk_status pt_run_impl(const Relaxed& R, const sk_pt_params* p, hipStream_
     a.variant = R.variant;
     a.top = R.top;
     a.levels = M;
-    a.pset = R.pset;
     a.slot_bytes = slot_bytes;
     a.seed = p->seed;
     a.move_thr = D.mt;
@@ -295,13 +299,25 @@ static sk_status pt_run_impl(const Relaxed& R, const sk_pt_params* p, hipStream_
                 PT_OK(learned_move(net, D, n, M, j0, chains, p->seed, (uint32_t)learned_moves, stream));
                 ++learned_moves;
             }
+            if (D.h1 && ex->first_iters == 0 && 2 * done >= p->iterations) {
+                PT_HIP(hipMemcpyAsync(D.h1, D.h, nh * sizeof(uint64_t), hipMemcpyDeviceToDevice, stream));
+                ex->first_iters = done;
+            }
         }
         // energies of the configurations the last learned move left
         if (learned_moves > 0) PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it, stream, true));
     } else {
         PT_OK(clear_stats(D, nh, nl, stream));
-        PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it + p->iterations, stream));
-        it += p->iterations;
+        // with the halves wanted, the histograms after the first half are copied
+        const uint64_t first = D.h1 ? p->iterations / 2 : p->iterations;
+        PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it + first, stream));
+        it += first;
+        if (D.h1) {
+            PT_HIP(hipMemcpyAsync(D.h1, D.h, nh * sizeof(uint64_t), hipMemcpyDeviceToDevice, stream));
+            ex->first_iters = first;
+            PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it + (p->iterations - first), stream));
+            it += p->iterations - first;
+        }
     }
     PT_OK(enqueue_plain(D, a, Lad, lds, seg, it, it, stream));  // zero iterations: initial states
     PT_OK(elapsed(D, stream, gpu_ms));
@@ -311,6 +327,10 @@ static sk_status pt_run_impl(const Relaxed& R, const sk_pt_params* p, hipStream_
     PT_HIP(hipMemcpyAsync(swap_acc, D.sw, nl * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
     if (state) PT_HIP(hipMemcpyAsync(state, D.cur, nst, hipMemcpyDeviceToHost, stream));
     if (energy) PT_HIP(hipMemcpyAsync(energy, D.e, nl * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    if (D.h1) {
+        ex->hist_first.resize(nh);
+        PT_HIP(hipMemcpyAsync(ex->hist_first.data(), D.h1, nh * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+    }
     if (ex && D.la) {
         ex->learned_acc.resize(nl);
         PT_HIP(hipMemcpyAsync(ex->learned_acc.data(), D.la, nl * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
@@ -325,6 +345,45 @@ static sk_status pt_run_impl(const Relaxed& R, const sk_pt_params* p, hipStream_
     if (learned && L->params && L->train_steps > 0)
         PT_HIP(hipMemcpy(L->params, net.P, net.count * sizeof(float), hipMemcpyDeviceToHost));
     return SK_OK;
+}
+
+// Per ladder: Z(0) prod_j Ratio(j) (Sec. 3), the last ratio taken to
+// beta = infinity (fraction of samples with E = 0); halved for reflections.
+// Then the mean over the ladders and its standard error.
+static void estimate_of(const Relaxed& R, const sk_pt_params* p, const uint64_t* hist, bool halve, double& mean,
+                        double& se)
+{
+    const int M = p->levels, Lad = p->ladders, H = R.top + 1;
+    double logz0 = 0;
+    for (int x : R.L) logz0 += std::log((double)x);
+    std::vector<double> est(Lad);
+    for (int l = 0; l < Lad; ++l) {
+        double lg = logz0;
+        bool zero = false;
+        for (int j = 0; j < M; ++j) {
+            const uint64_t* h = &hist[((size_t)l * M + j) * H];
+            double tot = 0, num = 0;
+            for (int e = 0; e < H; ++e) tot += (double)h[e];
+            if (j + 1 < M) {
+                const double db = p->beta[j + 1] - p->beta[j];
+                for (int e = 0; e < H; ++e) num += (double)h[e] * std::exp(-db * e);
+            } else {
+                num = (double)h[0];
+            }
+            if (num <= 0 || tot <= 0) {
+                zero = true;
+                break;
+            }
+            lg += std::log(num / tot);
+        }
+        est[l] = zero ? 0.0 : std::exp(lg) * (halve ? 0.5 : 1.0);
+    }
+    mean = 0;
+    for (double x : est) mean += x;
+    mean /= Lad;
+    double var = 0;
+    for (double x : est) var += (x - mean) * (x - mean);
+    se = Lad > 1 ? std::sqrt(var / (Lad - 1) / Lad) : 0.0;
 }
 
 static sk_status check_params(const Relaxed& R, const sk_pt_params* p)
@@ -399,47 +458,37 @@ sk_status sk_approx(int n, int variant, const sk_pt_params* p, void* stream, dou
         st = own;
     }
     PtExtra ex;
+    ex.want_half = p->iterations >= 2;
     s = pt_run_impl(R, p, st, hist.data(), ma.data(), sw.data(), nullptr, nullptr, &ex);
     if (own) (void)hipStreamDestroy(own);
     if (s != SK_OK) return s;
 
-    // Z(0) = prod_k L_k; per ladder: Z(0) prod_j Ratio(j) (Sec. 3), the last
-    // ratio taken to beta = infinity (fraction of samples with E = 0).
-    double logz0 = 0;
-    for (int x : R.L) logz0 += std::log((double)x);
+    // Z(0) = prod_k L_k times the ratios of every ladder; mean and standard error
     const bool halve = !(p->flags & SK_ORDERED) && variant != SK_HOOKED && n > 1;
-    std::vector<double> est(Lad);
-    for (int l = 0; l < Lad; ++l) {
-        double lg = logz0;
-        bool zero = false;
-        for (int j = 0; j < M; ++j) {
-            const uint64_t* h = &hist[((size_t)l * M + j) * H];
-            double tot = 0, num = 0;
-            for (int e = 0; e < H; ++e) tot += (double)h[e];
-            if (j + 1 < M) {
-                const double db = p->beta[j + 1] - p->beta[j];
-                for (int e = 0; e < H; ++e) num += (double)h[e] * std::exp(-db * e);
-            } else {
-                num = (double)h[0];
-            }
-            if (num <= 0 || tot <= 0) {
-                zero = true;
-                break;
-            }
-            lg += std::log(num / tot);
-        }
-        est[l] = zero ? 0.0 : std::exp(lg) * (halve ? 0.5 : 1.0);
+    double mean = 0, se = 0;
+    estimate_of(R, p, hist.data(), halve, mean, se);
+    // the same from each half of the recorded iterations: a short run whose
+    // chains are still equilibrating gives halves that differ by more than
+    // their standard errors allow (the bias is common to all ladders, so the
+    // spread between ladders does not show it)
+    double half_est[2] = {0, 0}, half_se[2] = {0, 0}, half_z = 0;
+    if (!ex.hist_first.empty() && ex.first_iters > 0 && ex.first_iters < p->iterations) {
+        std::vector<uint64_t> second(hist.size());
+        for (size_t i = 0; i < hist.size(); ++i) second[i] = hist[i] - ex.hist_first[i];
+        estimate_of(R, p, ex.hist_first.data(), halve, half_est[0], half_se[0]);
+        estimate_of(R, p, second.data(), halve, half_est[1], half_se[1]);
+        const double den = std::sqrt(half_se[0] * half_se[0] + half_se[1] * half_se[1]);
+        half_z = den > 0 ? (half_est[1] - half_est[0]) / den : 0.0;
     }
-    double mean = 0;
-    for (double x : est) mean += x;
-    mean /= Lad;
-    double var = 0;
-    for (double x : est) var += (x - mean) * (x - mean);
-    const double se = Lad > 1 ? std::sqrt(var / (Lad - 1) / Lad) : 0.0;
     *estimate = mean;
     if (std_error) *std_error = se;
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
+        stats->estimate_half[0] = half_est[0];
+        stats->estimate_half[1] = half_est[1];
+        stats->std_error_half[0] = half_se[0];
+        stats->std_error_half[1] = half_se[1];
+        stats->half_z = half_z;
         stats->levels = M;
         stats->ladders = Lad;
         stats->gpu_ms = ex.gpu_ms;
@@ -473,6 +522,80 @@ sk_status sk_approx(int n, int variant, const sk_pt_params* p, void* stream, dou
             }
         }
         stats->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return SK_OK;
+}
+
+sk_status sk_pt_tune_ladder(int n, int variant, double beta_max, double target, int max_levels, int ladders,
+                            uint64_t pilot_iterations, uint64_t seed, void* stream, double* beta_out,
+                            int* levels_out, double* accept_out)
+{
+    Relaxed R;
+    if (!relaxed_of(n, variant, R) || !beta_out || !levels_out) return SK_EINVAL;
+    if (!(beta_max > 0) || !std::isfinite(beta_max) || !(target > 0 && target < 1) || max_levels < 2 ||
+        max_levels > kPtMaxLevels || ladders < 1 || pilot_iterations < 2)
+        return SK_EINVAL;
+    for (int x : R.L)
+        if (x == 0) return SK_EINVAL;
+    if (hipSetDevice(current_device()) != hipSuccess) return SK_EDEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    hipStream_t own = nullptr;
+    if (!st) {
+        if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) return SK_EDEVICE;
+        st = own;
+    }
+    std::vector<double> beta = {0.0, beta_max};
+    std::vector<double> acc;
+    sk_status s = SK_OK;
+    for (int round = 0; round < 64; ++round) {
+        const int M = (int)beta.size();
+        sk_pt_params p;
+        std::memset(&p, 0, sizeof(p));
+        p.levels = M;
+        p.beta = beta.data();
+        p.ladders = ladders;
+        p.iterations = pilot_iterations;
+        p.burn_in = pilot_iterations;
+        p.seed = seed + (uint64_t)round;
+        p.proposal = SK_PROPOSAL_UNIFORM;
+        const int H = R.top + 1;
+        std::vector<uint64_t> hist((size_t)ladders * M * H), ma((size_t)ladders * M), sw((size_t)ladders * M);
+        s = pt_run_impl(R, &p, st, hist.data(), ma.data(), sw.data(), nullptr, nullptr, nullptr);
+        if (s != SK_OK) break;
+        // pooled acceptance of the exchange (j, j+1), attempted on every other iteration
+        acc.assign(M - 1, 0.0);
+        for (int j = 0; j + 1 < M; ++j) {
+            double swa = 0;
+            for (int l = 0; l < ladders; ++l) swa += (double)sw[(size_t)l * M + j];
+            const double tries = (double)ladders * (double)((pilot_iterations + ((j & 1) ? 0 : 1)) / 2);
+            acc[j] = tries > 0 ? swa / tries : 0.0;
+        }
+        // a level in the middle of every pair below the target, lowest
+        // acceptance first while levels remain
+        std::vector<int> low;
+        for (int j = 0; j + 1 < M; ++j)
+            if (acc[j] < target) low.push_back(j);
+        if (low.empty() || M >= max_levels) break;
+        std::sort(low.begin(), low.end(), [&](int x, int y) { return acc[x] < acc[y]; });
+        if ((int)low.size() > max_levels - M) low.resize(max_levels - M);
+        std::sort(low.begin(), low.end());
+        std::vector<double> nb;
+        size_t li = 0;
+        for (int j = 0; j < M; ++j) {
+            nb.push_back(beta[j]);
+            if (li < low.size() && low[li] == j) {
+                nb.push_back(beta[j] == 0.0 ? 0.5 * beta[j + 1] : std::sqrt(beta[j] * beta[j + 1]));
+                ++li;
+            }
+        }
+        beta.swap(nb);
+    }
+    if (own) (void)hipStreamDestroy(own);
+    if (s != SK_OK) return s;
+    *levels_out = (int)beta.size();
+    for (size_t j = 0; j < beta.size(); ++j) beta_out[j] = beta[j];
+    if (accept_out) {
+        for (size_t j = 0; j < beta.size(); ++j) accept_out[j] = j < acc.size() ? acc[j] : 0.0;
     }
     return SK_OK;
 }

@@ -50,6 +50,9 @@ struct ExactArgs {
     int32_t qb[5];               // product group g covers quads [qb[g], qb[g+1])
     unsigned long long* acc;     // device: nprimes x (low word, carries) sums of the
                                  // waves' residues in [0, p); nullptr: one output row per wave
+    int32_t larsen;              // 1: the inclusion-exclusion sum (0/1 variables, see exact_v2_body.h)
+    int32_t pad1;
+    uint64_t x_extra;            // bits ORed into every sign mask (position 1's value for larsen)
 };
 
 // Reversal weights (Lemma 2.3).  For Skolem and Langford pairings the term
@@ -82,6 +85,7 @@ struct ExactArgsV2 {
     const uint64_t* chunk_ids;   // device array, one chunk id per wave, or nullptr
     uint64_t n_waves;            // waves with work in this launch
     unsigned long long* acc;     // as ExactArgs::acc
+    uint64_t x_extra;            // as ExactArgs::x_extra
 };
 
 // Device accumulators of one pass: at most this many primes (several launch

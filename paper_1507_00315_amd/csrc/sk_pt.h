@@ -7,10 +7,10 @@
 namespace sk {
 
 constexpr int kPtMaxLevels = 64;
+constexpr int kPtMaxN = 40;  // pairs (positions up to 2n + 1 <= 81, bytes in LDS)
 
 struct PtArgs {
     int32_t n, variant, top, levels;
-    uint64_t pset;            // bit p-1 set for every position p of P
     int32_t slot_bytes;       // LDS bytes per configuration slot
     uint32_t ladder_base;     // ladder id of block 0
     uint64_t seed;

@@ -49,6 +49,15 @@ def test_counts_small_n_all_variants(variant):
         assert got == want, (variant, n, got, want)
 
 
+def test_reported_counts_at_n1():
+    """S(1) = 1: the one pairing is its own reflection and is not halved
+    (Sec. 1.3 halves for n > 1); L(1) = 0; the sum is evaluated."""
+    assert sk.count(1, "skolem", no_shortcut=True) == 1
+    assert sk.count(1, "skolem", ordered=True, no_shortcut=True) == 1
+    assert sk.count(1, "langford", no_shortcut=True) == 0
+    assert sk.count_larsen(1, "skolem", no_shortcut=True).count == 1
+
+
 def test_config1_skolem_12_and_zeros():
     """S(12) over 2^23 sign vectors, two primes; S(10) = S(11) = 0 (Table 7;
     existence, Sec. 1.1)."""
@@ -329,3 +338,26 @@ def test_caller_workspace_gives_the_same_results():
         sk.partial_chunks(16, "skolem", 10, ids, PRIMES[:2], workspace=(wp.data_ptr(), pb - 1))
     assert ei.value.status == -5
     torch.cuda.synchronize()
+
+
+def test_batch_groups_and_one_prime_per_item():
+    """Instances of three batched groups in one call (n = 12, 13; the other
+    14 <= n <= 21; the mixed set), one persistent launch per group: printed
+    and stored oracle values, sums that must vanish where no pairing exists
+    (shortcut off), and hooked n = 18 against its separate count.  Then the
+    mixed set with one prime per work item (group 1's second kernel)."""
+    g = _load("oracle_counts.json")
+    h18 = sk.count(18, "hooked", ordered=True)
+    inst = [(12, "skolem"), (13, "skolem"), (12, "langford"), (13, "hooked", sk.ORDERED),
+            (18, "skolem", sk.NO_SHORTCUT), (17, "langford", sk.NO_SHORTCUT), (16, "hooked", sk.NO_SHORTCUT),
+            (18, "hooked", sk.ORDERED), (16, "skolem"), (15, "langford")]
+    counts, st = sk.count_batch(inst, tuning={"log2_chunk_terms": 24, "waves_per_launch": 4096})
+    want = [227968, 1520280, 108144, int(g["hooked:13"]["ordered"]), 0, 0, 0, h18, 700078384, 39809640]
+    assert counts == want
+    # three group launches, and one reference-body launch for L(12), whose walk
+    # is too short for the tuned body
+    assert sk.describe(12, "langford")["n_walk"] < 5
+    assert st["launches"] == 4
+    one, st1 = sk.count_batch(MIXED, tuning={"log2_chunk_terms": 24, "waves_per_launch": 4096, "primes_per_item": 1})
+    assert one == [_expected(n, v) for n, v in MIXED]
+    assert st1["launches"] == 1

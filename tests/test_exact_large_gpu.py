@@ -39,21 +39,20 @@ def _ready():
     sk.lib()
 
 
-@pytest.mark.parametrize("variant,n", [("langford", 23), ("skolem", 24), ("langford", 24)])
-def test_printed_counts_n23_n24(variant, n):
-    """Full exact counts with both symmetries (Lemma 2.3, Lemma 2.4) against
-    the printed values; the ordered count is twice the printed one (Sec. 1.3)
-    and, where Table 4 prints it, equal to that column."""
+def test_printed_counts_n23_n24():
+    """L(23), S(24), L(24) as full exact counts with both symmetries (Lemma
+    2.3, Lemma 2.4) in one persistent launch (their batched group), against
+    the printed values (Tables 7 and 8); the ordered counts are twice the
+    printed ones (Sec. 1.3) and equal Table 4's for S(24)."""
     paper = _load("paper_counts.json")
-    want = int(paper[variant][str(n)])
-    _say("full count", variant, n)
-    r = sk.count_ex(n, variant, ordered=True)
-    _say(f"  {r.count}  kernel {r.stats['kernel_ms'] / 1e3:.1f} s  body {r.stats['kernel_variant']}")
-    assert r.stats["kernel_variant"] == 2  # the tuned body for this n
-    assert r.count == 2 * want
-    ordered = paper.get(f"{variant}_ordered", {}).get(str(n))
-    if ordered is not None:
-        assert r.count == int(ordered)
+    inst = [(23, "langford", sk.ORDERED), (24, "skolem", sk.ORDERED), (24, "langford", sk.ORDERED)]
+    _say("full counts L(23), S(24), L(24) in one batched launch")
+    counts, st = sk.count_batch(inst, tuning={"log2_chunk_terms": 30, "waves_per_launch": 8192})
+    _say(f"  {counts}  kernel {st['kernel_ms'] / 1e3:.1f} s, launches {st['launches']}")
+    assert st["launches"] == 1 and st["kernel_variant"] == 3
+    for (n, v, _), c in zip(inst, counts):
+        assert c == 2 * int(paper[v][str(n)]), (v, n)
+    assert counts[1] == int(paper["skolem_ordered"]["24"])
 
 
 @pytest.mark.parametrize("variant", ["skolem", "langford"])

@@ -77,6 +77,21 @@ def test_printed_langford_values_small(n):
     assert O.reported(O.count_backtrack(n, "langford", threads=8), n, "langford") == int(g[str(n)])
 
 
+def test_n1_conventions():
+    """n = 1 (Sec. 1.3 halves for reflections only when n > 1): the single
+    Skolem pairing (1, 2) is its own reflection, so S(1) = 1 = C(1); no
+    Langford pairing has positions 1, 2 at distance 2, so L(1) = 0; the hooked
+    set {1, 3} holds the pair (1, 3) only at distance 2, so H(1) = 0."""
+    assert O.enumerate_pairings(1, "skolem") == [(1,)]
+    assert O.count_backtrack(1, "skolem") == 1 and O.reported(1, 1, "skolem") == 1
+    assert O.count_backtrack(1, "langford") == 0 and O.reported(0, 1, "langford") == 0
+    assert O.count_backtrack(1, "hooked") == 0
+    # n > 1: every pairing has a distinct reflection, so ordered counts are even
+    assert O.reported(6, 4, "skolem") == 3 and O.reported(2, 3, "langford") == 1
+    with pytest.raises(AssertionError):
+        O.reported(7, 4, "skolem")
+
+
 def test_table4_ordered_is_twice_reported():
     g = _load("paper_counts.json")
     for n, v in g["skolem_ordered"].items():

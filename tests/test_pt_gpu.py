@@ -99,3 +99,47 @@ def test_burn_in_is_not_recorded_and_continues_the_chains():
         for j in range(len(betas)):
             assert [a - b for a, b in zip(full["hist"][lad][j], head["hist"][lad][j])] == tail["hist"][lad][j]
         assert tail["state"][lad] == full["state"][lad] and tail["energy"][lad] == full["energy"][lad]
+
+
+@pytest.mark.parametrize("variant,n", [("skolem", 33), ("langford", 32), ("hooked", 40)])
+def test_chains_bit_exact_beyond_64_positions(variant, n):
+    """Instances with more than 64 positions (S(33) of Table 7 among them)
+    run the same chains as the oracle."""
+    betas = [0.0] + [0.05 * 120 ** (j / 15) for j in range(16)]
+    g = sk.pt_run(n, variant, betas, 2, 1500, 99)
+    for lad in range(2):
+        o = O.pt_ladder(n, variant, betas, 1500, 99, ladder=lad, schedule="even_odd")
+        assert g["hist"][lad] == o["hist"] and g["state"][lad] == o["final_a"]
+        assert g["energy"][lad] == o["final_e"]
+
+
+def test_half_split_flags_unequilibrated_runs():
+    """The two halves of a run: an equilibrated run (burn-in, many
+    iterations) gives halves within their errors; a short run recorded from
+    the first iteration (as Algorithm 2 is printed) on a large instance gives
+    a first half biased low, flagged by half_z."""
+    betas = [0.0] + [0.25 * 1.45 ** i for i in range(12)]
+    est, se, st = sk.approx(12, "skolem", betas, ladders=64, iterations=1 << 17, seed=11, burn_in=1 << 15)
+    _say("equilibrated halves", st["estimate_half"], st["std_error_half"], st["half_z"])
+    assert abs(st["half_z"]) < 4
+    assert all(abs(h - 227968) < 6 * e for h, e in zip(st["estimate_half"], st["std_error_half"]))
+    ladder = [0.0] + [0.05 * 120.0 ** (j / 47) for j in range(48)]
+    est, se, st = sk.approx(24, "skolem", ladder, ladders=256, iterations=1 << 12, seed=12)
+    _say("short run halves", st["estimate_half"], st["std_error_half"], st["half_z"], est, se)
+    assert st["half_z"] > 3 and st["estimate_half"][0] < st["estimate_half"][1]
+
+
+def test_tuned_ladder_meets_the_exchange_target():
+    """Sec. 3: exchanges of neighbouring levels accepted at least half the
+    time, with a limited number of levels; the tuned ladder then estimates
+    S(13) and L(12) within error."""
+    for variant, n in (("skolem", 13), ("langford", 12)):
+        betas, acc = sk.pt_tune_ladder(n, variant, 8.0, target=0.5, max_levels=64, ladders=128,
+                                       pilot_iterations=1 << 13, seed=5)
+        _say("tuned ladder", variant, n, len(betas), [round(b, 3) for b in betas], [round(a, 2) for a in acc])
+        assert betas[0] == 0.0 and betas[-1] == 8.0 and all(b > a for a, b in zip(betas, betas[1:]))
+        assert len(betas) < 64 and min(acc) >= 0.5
+        est, se, st = sk.approx(n, variant, betas, ladders=128, iterations=1 << 17, seed=21, burn_in=1 << 15)
+        exact = O.reported(O.count_backtrack(n, variant, threads=8), n, variant)
+        _say("  estimate", est, se, exact, "min swap accept", min(st["swap_accept"][:len(betas) - 1]))
+        assert abs(est - exact) < max(4 * se, 0.01 * exact)

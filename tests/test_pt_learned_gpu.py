@@ -126,3 +126,32 @@ def test_invalid_learned_parameters():
             sk.approx(6, "skolem", betas, 2, 16, 1, proposal=sk.PROPOSAL_LEARNED, learned=_learned(**kw))
     with pytest.raises(sk.SkolemError):
         sk.approx(6, "skolem", betas, 2, 16, 1, proposal=sk.PROPOSAL_LEARNED, learned=None)
+
+
+def test_learned_against_plain_tempering():
+    """What the learned proposal gains and loses against plain tempering (the
+    method without it: uniform moves, Sec. 3) on Table 6's S(12) ladder, at
+    the same recorded iterations and seed.  Gains: at the middle levels the
+    learned moves that change the configuration are accepted more often than
+    the uniform moves there (on average over those levels), and the estimate's
+    standard error is smaller.  Loss: the GPU time, since a learned move costs
+    two network evaluations per chain where a uniform move costs a few
+    instructions.  Both estimates are within error of the exact count."""
+    n = 12
+    it = 1 << 16
+    plain_est, plain_se, plain = sk.approx(n, "skolem", TABLE6_BETAS, ladders=128, iterations=it, seed=77,
+                                           burn_in=1 << 14)
+    est, se, st = sk.approx(n, "skolem", TABLE6_BETAS, ladders=128, iterations=it, seed=77,
+                            proposal=sk.PROPOSAL_LEARNED,
+                            learned=_learned(hidden1=128, hidden2=128, train_iterations=1 << 14, snapshots=8,
+                                             train_steps=600, minibatch=512))
+    mid = list(range(2, len(TABLE6_BETAS) - 3))
+    gain = [st["learned_accept"][j] / plain["move_accept"][j] for j in mid]
+    _say("learned/plain acceptance at the middle levels", [round(g, 2) for g in gain])
+    _say("GPU s: plain", plain["gpu_ms"] / 1e3, "learned", st["gpu_ms"] / 1e3,
+         "standard errors", plain_se, se, "estimates", plain_est, est)
+    assert sum(gain) / len(gain) > 1.2
+    assert se < plain_se
+    assert st["gpu_ms"] > 2 * plain["gpu_ms"]
+    for e, s in ((plain_est, plain_se), (est, se)):
+        assert abs(e - 227968) < max(4 * s, 0.01 * 227968)
