@@ -128,7 +128,9 @@ typedef struct {
 /* Progress callback: return nonzero to abort (the call then returns SK_EABORTED). */
 typedef int (*sk_progress_fn)(void *ctx, uint64_t terms_done, uint64_t terms_total);
 
-/* Selects the HIP device used by later calls of this thread (default 0). */
+/* Selects the HIP device used by later calls of this thread (default 0) and
+ * does the library's set-up for it (its stream, the fixed workspace of
+ * sk_count_batch_noalloc), if not done yet. */
 sk_status sk_set_device(int device);
 
 /*
@@ -234,6 +236,23 @@ sk_status sk_count_combine(int n, int variant, unsigned flags, const uint64_t *r
 sk_status sk_count_batch(const sk_instance *inst, size_t k, const sk_tuning *tune,
                          void *dev_workspace, size_t ws_bytes, void *stream,
                          sk_stats *stats, sk_u128 *out);
+
+/*
+ * sk_count_batch_noalloc -- sk_count_batch for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The device workspace is a fixed array of the
+ * library, 4096 bytes on each GPU it runs on, held until the process ends;
+ * the call makes no hipMalloc, hipFree, event or stream (the per-device
+ * set-up -- the library's stream and the array's address -- is done by
+ * sk_set_device, or else by the first call on a device).  Every call on one
+ * GPU uses that GPU's array and clears what it needs at its start: calls
+ * that overlap on one GPU (threads, streams) race and must not be made.
+ * stats->kernel_ms is the host-clock time of the launches (no events).
+ * Errors: as sk_count_batch; SK_ENOMEM if the instances need more workspace
+ * than the fixed array holds (sk_workspace_bytes).
+ */
+sk_status sk_count_batch_noalloc(const sk_instance *inst, size_t k, const sk_tuning *tune,
+                                 void *stream, sk_stats *stats, sk_u128 *out);
 
 /*
  * sk_autotune_batch -- times the batched launch of these instances, group by

@@ -157,6 +157,8 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(Stats), ctypes.POINTER(U128)]
     L.sk_count_larsen.argtypes = [c_int, c_int, c_uint, ctypes.POINTER(Tuning), vp, c_size, vp,
                                   ctypes.POINTER(Stats), ctypes.POINTER(U128)]
+    L.sk_count_batch_noalloc.argtypes = [ctypes.POINTER(Instance), c_size, ctypes.POINTER(Tuning), vp,
+                                         ctypes.POINTER(Stats), ctypes.POINTER(U128)]
     L.sk_workspace_bytes.argtypes = [ctypes.POINTER(Instance), c_size, ctypes.POINTER(Tuning)]
     L.sk_workspace_bytes.restype = c_size
     L.sk_partial_workspace_bytes.argtypes = [c_int, c_int, c_size, c_int, ctypes.POINTER(Tuning)]
@@ -181,7 +183,7 @@ def lib() -> ctypes.CDLL:
     L.sk_last_error.restype = ctypes.c_char_p
     L.sk_kernel_name.argtypes = [c_int]
     L.sk_kernel_name.restype = ctypes.c_char_p
-    for fn in ("sk_set_device", "sk_count", "sk_count_ex", "sk_sign_sum_residues", "sk_partial_chunks",
+    for fn in ("sk_set_device", "sk_count", "sk_count_ex", "sk_sign_sum_residues", "sk_partial_chunks", "sk_count_batch_noalloc",
                "sk_count_larsen", "sk_describe_larsen", "sk_pt_tune_ladder",
                "sk_max_chunk_bits", "sk_describe", "sk_count_batch", "sk_autotune_batch", "sk_pt_bins",
                "sk_pt_run", "sk_approx", "sk_last_stats", "sk_count_part", "sk_count_combine", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
@@ -192,7 +194,7 @@ def lib() -> ctypes.CDLL:
 
 
 EXPORTED = ["sk_set_device", "sk_count", "sk_count_ex", "sk_count_batch", "sk_autotune_batch", "sk_pt_bins",
-            "sk_workspace_bytes", "sk_partial_workspace_bytes", "sk_count_larsen", "sk_describe_larsen", "sk_pt_tune_ladder",
+            "sk_workspace_bytes", "sk_partial_workspace_bytes", "sk_count_batch_noalloc", "sk_count_larsen", "sk_describe_larsen", "sk_pt_tune_ladder",
             "sk_pt_run", "sk_approx", "sk_sign_sum_residues", "sk_partial_chunks",
             "sk_max_chunk_bits", "sk_describe", "sk_strerror", "sk_last_error", "sk_u128_to_decimal", "sk_kernel_name",
             "sk_last_stats", "sk_count_part", "sk_count_combine", "sk_mlp_param_count", "sk_mlp_init", "sk_mlp_forward", "sk_mlp_loss_grad", "sk_mlp_train",
@@ -357,6 +359,18 @@ def count_batch(instances, tuning: Optional[Dict] = None, stream=None, workspace
     wp, wb = _workspace(workspace)
     _check(lib().sk_count_batch(arr, len(instances), ctypes.byref(t) if t else None, wp, wb,
                                 _stream_handle(stream), ctypes.byref(st), out), "sk_count_batch")
+    return [o.value() for o in out], st.as_dict()
+
+
+def count_batch_noalloc(instances, tuning: Optional[Dict] = None, stream=None):
+    """count_batch on the library's fixed per-device workspace: the call
+    allocates no device memory (sk_count_batch_noalloc)."""
+    arr = _instances(instances)
+    out = (U128 * len(instances))()
+    st = Stats()
+    t = _tuning(tuning)
+    _check(lib().sk_count_batch_noalloc(arr, len(instances), ctypes.byref(t) if t else None,
+                                        _stream_handle(stream), ctypes.byref(st), out), "sk_count_batch_noalloc")
     return [o.value() for o in out], st.as_dict()
 
 
@@ -631,7 +645,7 @@ def last_stats_dict(st: Stats) -> Dict:
     return st.as_dict()
 
 
-__all__ = ["pt_tune_ladder", "count", "count_ex", "count_larsen", "count_batch", "workspace_bytes", "partial_workspace_bytes", "autotune_batch", "pt_run", "approx", "pt_bins", "sign_sum_residues",
+__all__ = ["pt_tune_ladder", "count", "count_ex", "count_larsen", "count_batch", "count_batch_noalloc", "workspace_bytes", "partial_workspace_bytes", "autotune_batch", "pt_run", "approx", "pt_bins", "sign_sum_residues",
            "partial_chunks", "last_stats", "count_part", "count_combine", "max_chunk_bits", "set_device", "mlp_param_count", "mlp_init", "mlp_forward",
            "mlp_loss_grad", "mlp_train", "mlp_mh_step", "PROPOSAL_UNIFORM", "PROPOSAL_LEARNED",
            "SkolemError", "SKOLEM", "LANGFORD", "HOOKED", "lib", "EXPORTED"]

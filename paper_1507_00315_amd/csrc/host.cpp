@@ -278,17 +278,25 @@ static sk_status make_plan(int n, int variant, Plan& P, bool larsen = false)
 
 // ------------------------------------------------------------------ device
 
+// Fixed device workspace of sk_count_batch_noalloc, for callers that cannot
+// allocate: every GPU the library runs on holds its own copy until the
+// process ends.  In host code this name is only a handle for
+// hipGetSymbolAddress; the device address is DeviceCtx::scratch.
+constexpr size_t kScratchBytes = 4096;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct DeviceCtx {
     bool ready = false;
     hipStream_t stream = nullptr;
     int cus = 0;
+    void* scratch = nullptr;  // this device's copy of `scratch`
 };
 
 static DeviceCtx g_ctx[64];
 static std::mutex g_ctx_mu;
 
 // Per-device set-up, once per device with that device current: the library's
-// stream and the CU count.
+// stream, the CU count and the address of the fixed workspace.
 static sk_status device_ctx(DeviceCtx** out)
 {
     if (g_device < 0 || g_device >= 64) return SK_EINVAL;
@@ -299,6 +307,9 @@ static sk_status device_ctx(DeviceCtx** out)
         hipDeviceProp_t prop;
         SK_HIP(hipGetDeviceProperties(&prop, g_device));
         c.cus = prop.multiProcessorCount;
+        void* addr = nullptr;
+        SK_HIP(hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)));
+        c.scratch = addr;
         SK_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
         c.ready = true;
     }
@@ -968,7 +979,8 @@ sk_status sk_set_device(int device)
     if (hipGetDeviceCount(&count) != hipSuccess) return SK_EDEVICE;
     if (device < 0 || device >= count) return SK_EINVAL;
     g_device = device;
-    return SK_OK;
+    DeviceCtx* ctx;
+    return device_ctx(&ctx);
 }
 
 static sk_status count_impl(int n, int variant, unsigned flags, const sk_tuning* tune, void* ws, size_t ws_bytes,
@@ -1299,6 +1311,23 @@ sk_status sk_count_batch(const sk_instance* inst, size_t k, const sk_tuning* tun
                          size_t ws_bytes, void* stream, sk_stats* stats, sk_u128* out)
 {
     return batch_impl(inst, k, tune, dev_workspace, ws_bytes, stream, stats, out, true);
+}
+
+sk_status sk_count_batch_noalloc(const sk_instance* inst, size_t k, const sk_tuning* tune, void* stream,
+                                 sk_stats* stats, sk_u128* out)
+{
+    if (!inst || !out || k == 0) return SK_EINVAL;
+    const size_t need = sk_workspace_bytes(inst, k, tune);
+    if (need == 0) return SK_EINVAL;
+    if (need > kScratchBytes) {
+        g_last_error = "needs " + std::to_string(need) + " bytes of device workspace; the fixed workspace holds " +
+                       std::to_string(kScratchBytes);
+        return SK_ENOMEM;
+    }
+    DeviceCtx* ctx;
+    sk_status s = device_ctx(&ctx);
+    if (s != SK_OK) return s;
+    return batch_impl(inst, k, tune, ctx->scratch, kScratchBytes, stream, stats, out, false);
 }
 
 size_t sk_workspace_bytes(const sk_instance* inst, size_t k, const sk_tuning* tune)
