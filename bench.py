@@ -76,14 +76,11 @@ KERNEL_SOURCES = {
     "exact_v2_kernel": ["exact_v2_inst.hip", "exact_v2_body.h", "exact_common.h", "sk_plan.h", "sk_internal.h"],
 }
 MEASURED_TRAFFIC = {
-    # (kernel, workload, log2 sign vectors per work item, waves per launch):
+    # (kernel, workload or leg, log2 sign vectors per work item, waves per launch):
     #     (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact_batch_kernel", "batch", 24, 4096): ("a519d991164ffec3", 3366.0, 6554.65625),
-    ("exact_batch_kernel", "batch", 24, 6144): ("a519d991164ffec3", 3371.625, 6619.375),
-    ("exact_batch_kernel", "batch", 24, 8192): ("a519d991164ffec3", 3356.3125, 6683.25),
-    ("exact_batch_kernel", "batch", 22, 6144): ("a519d991164ffec3", 11385.5, 25929.875),
-    ("exact_batch_kernel", "batch", 22, 8192): ("a519d991164ffec3", 11399.8125, 25992.53125),
-    ("exact_v2_kernel", "s20", 25, 0): ("5996699165dbafe6", 158.5, 128.0),
+    ("exact_batch_kernel", "batch", 22, 6144): ("b7eeb1ea4b6d7862", 1222.9375, 13246.5625),
+    ("exact_v2_kernel", "skolem:24 slice", 26, 8192): ("90787bfd0117604f", 368.4375, 128.0),
+    ("exact_v2_kernel", "langford:24 slice", 26, 8192): ("90787bfd0117604f", 366.0, 128.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
@@ -254,10 +251,12 @@ def cpu_model() -> str:
     return "unknown"
 
 
-# The paper's own tempering estimates beyond the exact counts (Table 7: S(32),
-# S(33); Table 8: L(31), L(32)), for context beside ours.
+# The paper's own tempering estimates at its frontier (Table 7: S(28), S(29),
+# exact values known, and S(32), S(33); Table 8: L(27), L(28), exact values
+# known, and L(31), L(32)), for context beside ours.
 PAPER_PT_ESTIMATES = {("skolem", 32): 2.213e26, ("skolem", 33): 3.614e27, ("langford", 31): 5.381e24,
-                      ("langford", 32): 8.812e25}
+                      ("langford", 32): 8.812e25, ("skolem", 28): 3.523e21, ("skolem", 29): 5.294e22,
+                      ("langford", 27): 1.115e20, ("langford", 28): 1.603e21}
 
 
 def pt_bench(sk, want, plain_iters, learned_iters, tuned_iters, ladders: int, learned_cfg: dict, seed: int = 1507,
@@ -319,12 +318,23 @@ def pt_bench(sk, want, plain_iters, learned_iters, tuned_iters, ladders: int, le
         tuned[n] = {"betas": betas, "swap_accept": acc, "tuning_wall_s": time.time() - t0}
         log(f"tuned ladder S({n}): {len(betas)} levels, min exchange acceptance {min(acc):.3f} "
             f"({time.time() - t0:.1f} s)")
+        # the same construction run on to 64 levels (the lowest acceptance split
+        # first): a wavefront has 64 lanes, so levels up to 64 cost no time
+        b64, acc64 = sk.pt_tune_ladder(n, "skolem", fixed[-1], target=0.999, max_levels=64, ladders=256,
+                                       pilot_iterations=1 << 14, seed=seed)
+        tuned[n]["betas_64"] = b64
+        tuned[n]["swap_accept_64"] = acc64
+        log(f"64-level ladder S({n}): min exchange acceptance {min(acc64):.3f}")
         for it in plain_iters:
             one("skolem", n, "plain", it, fixed)
         for it in learned_iters:
             one("skolem", n, "learned", it, fixed)
         for it in tuned_iters:
             one("skolem", n, "plain_tuned_ladder", it, betas)
+        for it in tuned_iters:
+            one("skolem", n, "plain_tuned_64", it, b64)
+    # the frontier: the largest counts the paper has exactly (Table 4, Tables 7
+    # and 8) and its estimates beyond them
     for variant, n in PAPER_PT_ESTIMATES:
         one(variant, n, "plain", plain_iters[-1], fixed)
     # per curve: the least GPU time whose estimate was within 1 % of exact
@@ -525,38 +535,45 @@ def main():
             terms = None
         return per, terms, ring_ops_per_term(n, d["primes"])
 
-    legs = []  # (name, kernel, terms per step, VALU instr per step, ring ops per step, results index)
+    # (name, kernel, terms per step, VALU instr per step, ring ops per step,
+    #  results index, key of the measured traffic or None)
+    legs = []
     if slice_ids is not None:
         per, _, ring = design_instr("langford", 28, False)
         legs.append(("langford:28 slice", sk.kernel_name(results[0][0][3]["kernel_variant"]), terms_per_step,
-                     per * terms_per_step, ring * terms_per_step, 0))
+                     per * terms_per_step, ring * terms_per_step, 0, None))
     elif batched:
         instr = ring = 0
         for v, n in instances:
             per, terms, rg = design_instr(v, n, True)
             instr += per * terms
             ring += rg * terms
-        legs.append(("batch", "exact_batch_kernel", results[0][0][3]["terms"], instr, ring, 0))
+        legs.append(("batch", "exact_batch_kernel", results[0][0][3]["terms"], instr, ring, 0,
+                     ("exact_batch_kernel", "batch" if args.workload == "mixed" else args.workload,
+                      results[0][0][3]["log2_chunk_terms"], launch_waves)))
         for i, sl in enumerate(n24):
             per, _, rg = design_instr(sl["variant"], 24, False)
             t = results[0][1 + i][3]["terms"]
             legs.append((f"{sl['variant']}:24 slice", f"exact_v2_kernel<{sk.VARIANTS[sl['variant']]},24>", t,
-                         per * t, rg * t, 1 + i))
+                         per * t, rg * t, 1 + i,
+                         ("exact_v2_kernel", f"{sl['variant']}:24 slice", results[0][1 + i][3]["log2_chunk_terms"],
+                          len(sl["ids"]))))
     elif args.workload.startswith("larsen"):
         for i, (v, n) in enumerate(instances):
             d = sk.describe(n, v, larsen=True)
             d["primes_used"] = d["primes"]
             t = results[0][i][3]["terms"]
             legs.append((f"{v}:{n} inclusion-exclusion", sk.kernel_name(results[0][i][3]["kernel_variant"]), t,
-                         valu_per_term(d) * t, ring_ops_per_term(n, d["primes"]) * t, i))
+                         valu_per_term(d) * t, ring_ops_per_term(n, d["primes"]) * t, i, None))
     else:
         for i, (v, n) in enumerate(instances):
             per, terms, rg = design_instr(v, n, True)
             t = results[0][i][3]["terms"]
-            legs.append((f"{v}:{n}", sk.kernel_name(results[0][i][3]["kernel_variant"]), t, per * t, rg * t, i))
+            legs.append((f"{v}:{n}", sk.kernel_name(results[0][i][3]["kernel_variant"]), t, per * t, rg * t, i,
+                         None))
 
     rooflines = []
-    for name, kernel, terms, instr, ring, idx in legs:
+    for name, kernel, terms, instr, ring, idx, tkey in legs:
         kms = sum(st[idx][3]["kernel_ms"] for st in results) / args.steps
         launches = sum(st[idx][3]["launches"] for st in results) // args.steps
         sec = kms * 1e-3
@@ -566,15 +583,14 @@ def main():
                           "valu_instr_per_term": instr / terms, "terms_per_launch_step": terms,
                           "terms_per_s_kernel": terms / sec if sec > 0 else 0.0, "kernel_ms_per_step": kms,
                           "launches": launches, "avg_launch_ms": kms / max(launches, 1),
-                          "ring_ops_per_term": ring / terms})
+                          "ring_ops_per_term": ring / terms,
+                          "traffic": traffic_per_launch(*tkey) if tkey else None})
     # the dominant kernel: the single kernel with the largest time per step
     dom = max(rooflines, key=lambda r: r["avg_launch_ms"])
     st0 = results[0][0][3]
     log2_chunk = st0["log2_chunk_terms"]
     roofline = {"bound": "alu", "achieved": dom["achieved"], "peak": PEAK_LANE_OPS, "unit": "VALU lane-instr/s",
-                "frac": dom["frac"],
-                "traffic": traffic_per_launch(dom["kernel"].split("<")[0], "batch" if args.workload == "mixed"
-                                              else args.workload, log2_chunk, launch_waves),
+                "frac": dom["frac"], "traffic": dom["traffic"],
                 "kernel": dom["kernel"], "leg": dom["leg"], "valu_instr_per_term": dom["valu_instr_per_term"],
                 "terms_per_s_kernel": dom["terms_per_s_kernel"], "launches": dom["launches"],
                 "avg_launch_ms": dom["avg_launch_ms"],

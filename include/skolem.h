@@ -223,8 +223,9 @@ sk_status sk_count_combine(int n, int variant, unsigned flags, const uint64_t *r
  * larger prime count, are counted by separate launches in the same call.
  *   inst  : k instances (k >= 1); out: k counts, in order
  *   tune  : NULL = the shape found by sk_autotune_batch for this instance set
- *           (cached per GPU model), else log2_chunk_terms (sign vectors per work
- *           item) and waves_per_launch (persistent grid) are used
+ *           (cached per GPU model; without a cached shape 2^22 sign vectors
+ *           per work item and 8 waves per SIMD), else log2_chunk_terms (sign
+ *           vectors per work item) and waves_per_launch (persistent grid)
  *   dev_workspace, ws_bytes : see the conventions (sk_workspace_bytes)
  *   stats : NULL or receives the totals of the call
  * Reduction: each wavefront's residues are summed per instance and prime in
@@ -256,13 +257,15 @@ sk_status sk_count_batch_noalloc(const sk_instance *inst, size_t k, const sk_tun
 
 /*
  * sk_autotune_batch -- times the batched launch of these instances, group by
- * group, on a fraction of their work (about 2^36 sign vectors, at most 1/16)
+ * group, on a fraction of their work (1/4, less above 2^42 sign vectors)
  * for a grid of (sign vectors per work item) x (waves per SIMD) x (primes per
  * work item, where built), stores the fastest shape of each group in the cache
  * file ($SK_TUNE_CACHE, default ~/.cache/skolem_mi355x_tune.txt) keyed by GPU
  * model and instance set, and returns that of the group with the most sign
- * vectors.  best_rate (nullable) receives its sign vectors per second.
- * Errors: SK_ENOLIB if an instance has no batched kernel.
+ * vectors.  Instances that sk_count_batch counts by separate launches (no
+ * batched kernel, or no pairing exists) are left out.  best_rate (nullable)
+ * receives the returned shape's sign vectors per second.
+ * Errors: SK_ENOLIB if no instance of the set runs in a batched launch.
  */
 sk_status sk_autotune_batch(const sk_instance *inst, size_t k, void *stream, sk_tuning *best,
                             double *best_rate);

@@ -910,13 +910,15 @@ static std::string tune_key(const std::vector<const Plan*>& plans)
 }
 
 // Times the batched launch of one group's instances on a fraction of every
-// instance's chunks (about 2^36 sign vectors in all, at most 1/16) for each
-// candidate shape and keeps the fastest in sign vectors of the count per
-// second.  Candidates: 2^22 .. 2^28 sign vectors per work item, 2 .. 8
-// persistent waves per SIMD, and where the group has a kernel for it one prime
-// per work item instead of all of them.  Smaller work items balance the tail of
-// the launch better; one prime per item repeats the pair sums and products
-// for every prime.
+// instance's chunks (1/4, or less for groups above 2^40 sign vectors) for
+// each candidate shape and keeps the fastest in sign vectors of the count per
+// second.  The probe must be large: the tail of a launch (waves without
+// items) weighs as much more in a probe as the probe is smaller, and a small
+// probe favours fewer waves than the full launch wants.  Candidates: 2^22 ..
+// 2^28 sign vectors per work item, 2 .. 8 persistent waves per SIMD, and
+// where the group has a kernel for it one prime per work item instead of all
+// of them.  Smaller work items balance the tail of the launch better; one
+// prime per item repeats the pair sums and products for every prime.
 static sk_status autotune(const std::vector<const Plan*>& plans, int group, hipStream_t stream, BatchShape* best_out,
                           double* best_rate)
 {
@@ -925,8 +927,8 @@ static sk_status autotune(const std::vector<const Plan*>& plans, int group, hipS
     if (s != SK_OK) return s;
     uint64_t total = 0;
     for (auto* p : plans) total += 1ull << (p->m - 1 - (hat_symmetric(*p) ? 1 : 0));
-    int shift = 4;
-    while (shift < 20 && (total >> shift) > (1ull << 36)) ++shift;
+    int shift = 2;
+    while (shift < 20 && (total >> shift) > (1ull << 40)) ++shift;
     const int lcs[] = {22, 24, 26, 28};
     const int wps[] = {2, 4, 6, 8};
     double best = -1.0;
@@ -1189,6 +1191,26 @@ sk_status sk_count_ex(int n, int variant, unsigned flags, const sk_tuning* tune,
 }
 
 
+// Splits a batch into the instances of each batched group (at most
+// kBatchMaxInstances per group) and those counted by separate launches:
+// instances outside every group, with no tuned body, or with a tuning the
+// batched kernels cannot run (the reference body, more primes).  Instances
+// with no pairing (Sec. 1.1) are in neither list unless the shortcut is off.
+static void partition_batch(const sk_instance* inst, size_t k, const sk_tuning* tune,
+                            std::vector<std::vector<int>>& batched, std::vector<int>& separate)
+{
+    batched.assign(kBatchGroups, {});
+    separate.clear();
+    for (size_t i = 0; i < k; ++i) {
+        const bool needed = existence(inst[i].n, inst[i].variant) || (inst[i].flags & SK_NO_SHORTCUT);
+        if (!needed) continue;
+        const int g = batch_group(inst[i].variant, inst[i].n);
+        const bool can = g >= 0 && !(tune && (tune->kernel == 1 || tune->primes > primes_for(inst[i].n)));
+        if (can && (int)batched[g].size() < kBatchMaxInstances) batched[g].push_back((int)i);
+        else separate.push_back((int)i);
+    }
+}
+
 // sk_count_batch on a given device workspace (nullptr: each launch allocates
 // its own); timing = false times the call by the host clock instead of HIP
 // events.
@@ -1211,16 +1233,9 @@ static sk_status batch_impl(const sk_instance* inst, size_t k, const sk_tuning* 
     std::memset(&st, 0, sizeof(st));
     std::vector<u128> result(k, 0);
     // instances of each batched group, and those counted by separate launches
-    std::vector<std::vector<int>> batched(kBatchGroups);
+    std::vector<std::vector<int>> batched;
     std::vector<int> separate;
-    for (size_t i = 0; i < k; ++i) {
-        const bool needed = existence(inst[i].n, inst[i].variant) || (inst[i].flags & SK_NO_SHORTCUT);
-        if (!needed) continue;
-        const int g = batch_group(inst[i].variant, inst[i].n);
-        const bool can = g >= 0 && !(tune && (tune->kernel == 1 || tune->primes > primes_for(inst[i].n)));
-        if (can && (int)batched[g].size() < kBatchMaxInstances) batched[g].push_back((int)i);
-        else separate.push_back((int)i);
-    }
+    partition_batch(inst, k, tune, batched, separate);
     DeviceCtx* ctx;
     {
         sk_status s = device_ctx(&ctx);
@@ -1230,8 +1245,11 @@ static sk_status batch_impl(const sk_instance* inst, size_t k, const sk_tuning* 
         if (batched[g].empty()) continue;
         std::vector<const Plan*> bp;
         for (int i : batched[g]) bp.push_back(&plans[i]);
+        // default shape when neither the caller nor the autotune cache has one:
+        // work items of 2^22 sign vectors, 8 persistent waves per SIMD
         BatchShape shape;
-        shape.waves = (uint64_t)ctx->cus * 4 * 2;
+        shape.log2_chunk = 22;
+        shape.waves = (uint64_t)ctx->cus * 4 * 8;
         if (tune && tune->log2_chunk_terms > 0) {
             shape.log2_chunk = tune->log2_chunk_terms;
             if (tune->waves_per_launch > 0) shape.waves = (uint64_t)tune->waves_per_launch;
@@ -1357,13 +1375,24 @@ sk_status sk_autotune_batch(const sk_instance* inst, size_t k, void* stream, sk_
 {
     if (!inst || k == 0 || !best) return SK_EINVAL;
     std::vector<Plan> plans(k);
-    std::vector<std::vector<const Plan*>> groups(kBatchGroups);
     for (size_t i = 0; i < k; ++i) {
         sk_status s = make_plan(inst[i].n, inst[i].variant, plans[i]);
         if (s != SK_OK) return s;
-        const int g = batch_group(inst[i].variant, inst[i].n);
-        if (g < 0) return SK_ENOLIB;
-        groups[g].push_back(&plans[i]);
+    }
+    // the groups sk_count_batch would launch for these instances; the ones it
+    // counts by separate launches have no shape to tune
+    std::vector<std::vector<int>> batched;
+    std::vector<int> separate;
+    partition_batch(inst, k, nullptr, batched, separate);
+    std::vector<std::vector<const Plan*>> groups(kBatchGroups);
+    bool any = false;
+    for (int g = 0; g < kBatchGroups; ++g) {
+        for (int i : batched[g]) groups[g].push_back(&plans[i]);
+        any = any || !groups[g].empty();
+    }
+    if (!any) {
+        g_last_error = "no instance of this set runs in a batched launch";
+        return SK_ENOLIB;
     }
     // every group is tuned and cached; the shape returned is that of the group
     // with the most sign vectors
@@ -1371,7 +1400,6 @@ sk_status sk_autotune_batch(const sk_instance* inst, size_t k, void* stream, sk_
     double out_rate = 0, most = -1;
     for (int g = 0; g < kBatchGroups; ++g) {
         if (groups[g].empty()) continue;
-        if (groups[g].size() > (size_t)kBatchMaxInstances) return SK_EINVAL;
         BatchShape shape;
         double rate = 0;
         sk_status s = autotune(groups[g], g, (hipStream_t)stream, &shape, &rate);

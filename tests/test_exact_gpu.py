@@ -236,11 +236,17 @@ def test_batch_with_unbatched_instances_and_zeros():
 
 
 def test_autotune_returns_a_working_shape():
-    inst = [(16, "skolem"), (16, "langford"), (15, "hooked")]
+    """The autotuner takes the sets count_batch takes: L(12) (no tuned body,
+    a separate launch) and S(18) (no pairing, Sec. 1.1) are left out of the
+    probes; a set with nothing to batch is an error."""
+    inst = [(16, "skolem"), (16, "langford"), (15, "hooked"), (12, "langford"), (18, "skolem")]
     best, rate = sk.autotune_batch(inst)
     assert best["log2_chunk_terms"] >= 20 and best["waves_per_launch"] > 0 and rate > 0
     counts, _ = sk.count_batch(inst)
-    assert counts == [_expected(n, v) for n, v in inst]
+    assert counts == [_expected(n, v) for n, v in inst[:4]] + [0]
+    with pytest.raises(sk.SkolemError) as e:
+        sk.autotune_batch([(12, "langford"), (10, "skolem")])
+    assert e.value.status == -7  # SK_ENOLIB
 
 
 def test_l28_slice_chunks_match_cpu_recomputation():
