@@ -81,9 +81,13 @@ typedef enum {
 typedef struct { uint64_t lo, hi; } sk_u128;
 
 /* Launch shape.  Zero in a field means "library default / autotuned".
- *   log2_chunk_terms : sign vectors evaluated by one wavefront (one chunk)
- *   waves_per_launch : wavefronts per kernel launch (the host splits the work
- *                      into launches of this many chunks)
+ *   log2_chunk_terms : sign vectors per chunk (the batched launch: per work item)
+ *   waves_per_launch : single counts: chunks per kernel launch (the host splits
+ *                      the work into launches of this many chunks; the tuned
+ *                      kernel's persistent waves, 8 per SIMD, pull small work
+ *                      items of the launch's chunks from a queue, the
+ *                      reference kernel runs one wavefront per chunk); the
+ *                      batched launch: its persistent wavefronts
  *   primes           : primes per pass for sk_count (1..4); default the fewest
  *                      whose product exceeds n! * 2^8 (n! bounds every count)
  *   kernel           : kernel body: 0 = the tuned body when built for the
@@ -179,8 +183,9 @@ size_t sk_workspace_bytes(const sk_instance *inst, size_t k, const sk_tuning *tu
 
 /*
  * sk_partial_workspace_bytes -- device workspace sk_partial_chunks needs for
- * nchunks chunks and nprimes primes with this launch shape: the accumulators,
- * one output row and one chunk id per wavefront of a launch.  0 on bad input.
+ * nchunks chunks and nprimes primes with this launch shape: the accumulators
+ * and work-queue counter, then one row of 128-bit sums and one chunk id per
+ * chunk of a launch.  0 on bad input.
  */
 size_t sk_partial_workspace_bytes(int n, int variant, size_t nchunks, int nprimes,
                                   const sk_tuning *tune);

@@ -143,8 +143,8 @@ __device__ __forceinline__ void add_u128_pair(unsigned long long* acc, unsigned 
     if (hi + carry) atomicAdd(acc + 1, hi + carry);
 }
 
-// Workgroup stage for one-chunk-per-wave launches (256 threads = 4
-// wavefronts, every thread of the workgroup must call it): the residues of the
+// Workgroup stage of the single-count launches (256 threads = 4 wavefronts,
+// every thread of the workgroup must call it): the residues of the
 // block's waves (res, the same in every lane of a wave; a wave with active ==
 // false contributes 0) meet in LDS, and one thread per prime adds their sum
 // (below 2^48) to acc[2 i], acc[2 i + 1].

@@ -372,12 +372,14 @@ struct ExactV2 {
     }
 };
 
-// One chunk (chunk id, 2^jb jobs) evaluated by the calling wavefront.
-// x_extra: bits ORed into every job's mask (position 1's value for LARSEN).
-// Returns in every lane the wave's residues (balanced, exact fp64 integers).
+// Jobs [j_begin, j_end) of one chunk (chunk id, 2^jb jobs) evaluated by the
+// calling wavefront and added to acc_tot (per lane, balanced residues: the
+// wave's sum is the sum over the lanes).  x_extra: bits ORed into every job's
+// mask (position 1's value for LARSEN).
 template <int V, int N, int P, int INNER, bool LARSEN = false>
-__device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const RevMasks& rev, const double (&pr)[P],
-                                               const double (&pinv)[P], double (&res)[P], uint64_t x_extra = 0)
+__device__ __forceinline__ void exact_v2_jobs(uint64_t chunk, int jb, uint64_t j_begin, uint64_t j_end,
+                                              const RevMasks& rev, const double (&pr)[P], const double (&pinv)[P],
+                                              double (&acc_tot)[P], uint64_t x_extra = 0)
 {
     using K = ExactV2<V, N, P, INNER, LARSEN>;
     constexpr PlanCE PL = K::PL;
@@ -396,13 +398,8 @@ __device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const Rev
     });
     const int lane_parity = __builtin_popcount(lane) & 1;
 
-    double acc_tot[P];
-#pragma unroll
-    for (int i = 0; i < P; ++i) acc_tot[i] = 0.0;
-
-    const uint64_t njobs = 1ull << jb;
     const uint64_t xu_chunk = (chunk << (1 + W + jb)) | x_extra;
-    for (uint64_t j = 0; j < njobs; ++j) {
+    for (uint64_t j = j_begin; j < j_end; ++j) {
         const uint64_t xu_job = xu_chunk | (j << (1 + W));
         // reversal weight of this job (wave-uniform: job variables only)
         int w = 1;
@@ -472,10 +469,20 @@ __device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const Rev
             acc_tot[i] = reduce_balanced(neg0 ? acc_tot[i] - aw : acc_tot[i] + aw, pr[i], pinv[i]);
         });
     }
-    static_for<0, P>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        res[i] = wave_sum_f64(acc_tot[i]);
-    });
+}
+
+// One whole chunk; returns in every lane the wave's residues (balanced, exact
+// fp64 integers).
+template <int V, int N, int P, int INNER, bool LARSEN = false>
+__device__ __forceinline__ void exact_v2_chunk(uint64_t chunk, int jb, const RevMasks& rev, const double (&pr)[P],
+                                               const double (&pinv)[P], double (&res)[P], uint64_t x_extra = 0)
+{
+    double acc[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) acc[i] = 0.0;
+    exact_v2_jobs<V, N, P, INNER, LARSEN>(chunk, jb, 0, 1ull << jb, rev, pr, pinv, acc, x_extra);
+#pragma unroll
+    for (int i = 0; i < P; ++i) res[i] = wave_sum_f64(acc[i]);
 }
 
 // A wave-uniform fp64 value copied into a vector register pair, so that it
@@ -495,28 +502,64 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
            (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
 }
 
+// Persistent launch: every wave pulls work items (2^item_job_bits jobs of one
+// chunk) from the launch's queue until it is empty.  Total mode (acc): each
+// wave keeps one running residue per prime over all its items, and the
+// workgroup adds the sums to the device accumulators at the end.  Row mode
+// (rows): each item's residues are added to its chunk's row.  Small items keep
+// every SIMD busy until the queue drains, whatever the number of waves that
+// fit on it.
 template <int V, int N, int P, int INNER, bool LARSEN = false>
-__global__ void __launch_bounds__(256) exact_v2_kernel(const ExactArgsV2 a, double* __restrict__ out)
+__global__ void __launch_bounds__(256) exact_v2_kernel(const ExactArgsV2 a)
 {
-    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const bool active = wave < a.n_waves;  // wave-uniform
-    double pr[P], pinv[P], res[P];
+    const int lane = threadIdx.x & 63;
+    double pr[P], pinv[P], tot[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         pr[i] = in_vgpr(a.prime[i]);
         pinv[i] = in_vgpr(a.pinv[i]);
-        res[i] = 0.0;
+        tot[i] = 0.0;
     }
-    if (active) {
-        const uint64_t chunk = uniform_u64(a.chunk_ids ? a.chunk_ids[wave] : a.chunk_base + wave);
-        exact_v2_chunk<V, N, P, INNER, LARSEN>(chunk, a.job_bits_per_chunk, a.rev, pr, pinv, res, a.x_extra);
-        if ((threadIdx.x & 63) == 0 && !a.acc) {
+    const int jb = a.job_bits_per_chunk;
+    const int ib = a.item_job_bits;
+    const int sub = jb - ib;  // items per chunk: 2^sub
+    bool any = false;
+    // A wave can claim at most n_items items; the trip bound guarantees that
+    // every wave leaves the loop whatever the counter returns.
+    for (uint32_t trip = 0; trip <= a.n_items; ++trip) {
+        // Every lane takes part in the atomic (lane 0 adds 1, the others 0) and
+        // the claimed index is read from lane 0: no lane-dependent branch
+        // precedes the broadcast.
+        const uint32_t old = atomicAdd(a.counter, lane == 0 ? 1u : 0u);
+        const uint32_t idx = __builtin_amdgcn_readlane(old, 0);
+        if (idx >= a.n_items) break;  // every wave leaves once the queue is empty
+        const uint64_t c = (uint64_t)idx >> sub;
+        const uint64_t j0 = ((uint64_t)idx & ((1ull << sub) - 1)) << ib;
+        const uint64_t chunk = uniform_u64(a.chunk_ids ? a.chunk_ids[c] : a.chunk_base + c);
+        double part[P];
 #pragma unroll
-            for (int i = 0; i < P; ++i) out[wave * P + i] = res[i];
+        for (int i = 0; i < P; ++i) part[i] = 0.0;
+        exact_v2_jobs<V, N, P, INNER, LARSEN>(chunk, jb, j0, j0 + (1ull << ib), a.rev, pr, pinv, part, a.x_extra);
+        if (a.rows) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const double r = wave_sum_f64(part[i]);
+                if (lane == 0) add_u128(a.rows + 2 * (c * P + i), canonical_residue(r, pr[i], pinv[i]));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < P; ++i) tot[i] = reduce_balanced(tot[i] + part[i], pr[i], pinv[i]);
+            any = true;
         }
     }
-    // sums of whole launches: workgroup stage, then the device accumulators
-    if (a.acc) workgroup_accumulate<P>(res, P, pr, pinv, active, a.acc);
+    if (a.acc) {
+        // sums of whole launches: wave butterfly, workgroup stage, then the
+        // device accumulators
+        double res[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) res[i] = wave_sum_f64(tot[i]);
+        workgroup_accumulate<P>(res, P, pr, pinv, any, a.acc);
+    }
 }
 
 }  // namespace sk

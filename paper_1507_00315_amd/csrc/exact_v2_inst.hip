@@ -12,7 +12,7 @@
 
 namespace sk {
 
-using ExactV2Fn = void (*)(const ExactArgsV2, double*);
+using ExactV2Fn = void (*)(const ExactArgsV2);
 int register_exact_v2(int variant, int n, int nprimes, int inner, bool larsen, ExactV2Fn fn);
 
 constexpr int kInner = 4;

@@ -355,24 +355,31 @@ struct SumRequest {
 };
 
 // Device workspace of run_sum: the accumulators of a total (kAccSlots
-// (low word, carries) pairs), then, for listed chunks, one output row of up
-// to kMaxPrimes residues and one chunk id per wave of a launch.
+// (low word, carries) pairs), the work-queue counter of a launch, then, for
+// listed chunks, one row of up to kMaxPrimes 128-bit sums (the reference
+// kernel: fp64 residues) and one chunk id per chunk of a launch.
 constexpr size_t kSumAccBytes = (size_t)kAccSlots * 2 * sizeof(unsigned long long);
+constexpr size_t kSumWsBytes = kSumAccBytes + 256;
 
 static size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static size_t sum_ws_bytes(bool listed, uint64_t waves_per_launch)
+static size_t sum_ws_bytes(bool listed, uint64_t chunks_per_launch)
 {
-    if (!listed) return kSumAccBytes;
-    return kSumAccBytes + round256(waves_per_launch * kMaxPrimes * sizeof(double)) +
-           round256(waves_per_launch * sizeof(uint64_t));
+    if (!listed) return kSumWsBytes;
+    return kSumWsBytes + round256(chunks_per_launch * kMaxPrimes * 2 * sizeof(unsigned long long)) +
+           round256(chunks_per_launch * sizeof(uint64_t));
 }
+
+// Work items of the tuned kernel: at least 2^kItemLog2Steps Gray-code steps
+// per lane (the claim of an item is one atomic round trip), otherwise as small
+// as possible, so that the queue drains evenly.
+constexpr int kItemLog2Steps = 14;
 
 hipError_t launch_zero_words(void* p, uint64_t n, hipStream_t stream);
 
 // ------------------------------------------------------------------ kernels
 
-using ExactV2Fn = void (*)(const ExactArgsV2, double*);
+using ExactV2Fn = void (*)(const ExactArgsV2);
 
 struct V2Entry {
     ExactV2Fn fn = nullptr;
@@ -476,18 +483,30 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
     if (stt != SK_OK) return stt;
     hipStream_t stream = R.stream ? R.stream : ctx->stream;
 
+    // chunks per launch (the reference kernel: one wave each)
     uint64_t wpl = R.waves_per_launch > 0 ? (uint64_t)R.waves_per_launch : (uint64_t)ctx->cus * 4 * 8;
     wpl = std::min<uint64_t>(wpl, nchunks);
+    // jobs per work item of the tuned kernel, 2^item_bits (kItemLog2Steps);
+    // a launch's items are counted in 32 bits
+    int item_bits = std::max(0, std::min(jb, kItemLog2Steps - P.n_walk));
+    {
+        int lw = 0;
+        while ((1ull << lw) < wpl) ++lw;
+        while (item_bits < jb && lw + (jb - item_bits) > 31) ++item_bits;
+    }
     if (np > kAccSlots || (uint64_t)nbatches * batch > (uint64_t)kAccSlots) return SK_EINVAL;
 
     const size_t need = sum_ws_bytes(listed, wpl);
     unsigned char* ws = (unsigned char*)R.ws;
     bool own_ws = false;
     unsigned long long* d_acc = nullptr;
-    double* d_out = nullptr;
+    uint32_t* d_counter = nullptr;
+    double* d_out = nullptr;              // listed rows of the reference kernel
+    unsigned long long* d_rows = nullptr; // listed rows of the tuned kernel (same memory)
     uint64_t* d_ids = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    std::vector<double> h_out(listed ? wpl * batch : 0);
+    std::vector<double> h_out(listed && kv == 1 ? wpl * batch : 0);
+    std::vector<unsigned long long> h_rows(listed && kv == 2 ? wpl * batch * 2 : 0);
     std::vector<unsigned long long> h_acc((size_t)2 * nbatches * batch);
     sk_status status = SK_OK;
     hipError_t e;
@@ -503,9 +522,11 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
         own_ws = true;
     }
     d_acc = (unsigned long long*)ws;
+    d_counter = (uint32_t*)(ws + kSumAccBytes);
     if (listed) {
-        d_out = (double*)(ws + kSumAccBytes);
-        d_ids = (uint64_t*)(ws + kSumAccBytes + round256(wpl * kMaxPrimes * sizeof(double)));
+        d_out = (double*)(ws + kSumWsBytes);
+        d_rows = (unsigned long long*)(ws + kSumWsBytes);
+        d_ids = (uint64_t*)(ws + kSumWsBytes + round256(wpl * kMaxPrimes * 2 * sizeof(unsigned long long)));
     } else if ((e = launch_zero_words(d_acc, 2 * (uint64_t)nbatches * batch, stream)) != hipSuccess) {
         fail(e, "zero accumulators");
         goto done;
@@ -556,8 +577,11 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
                 a2.pinv[i] = 1.0 / (double)bp[i];
             }
             a2.job_bits_per_chunk = jb;
+            a2.item_job_bits = item_bits;
             if (rev_r > 0) a2.rev = rev;
             a2.acc = acc;
+            a2.counter = d_counter;
+            a2.rows = listed ? d_rows : nullptr;
             a2.x_extra = x_extra;
         }
         for (uint64_t base = 0; base < nchunks; base += wpl) {
@@ -568,7 +592,18 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
                                         stream)) != hipSuccess) { fail(e, "hipMemcpyAsync"); goto done; }
                 ids = d_ids;
             }
-            const unsigned blocks = (unsigned)((nw + 3) / 4);
+            // reference kernel: one wave per chunk; tuned kernel: persistent
+            // waves (8 per SIMD, or one per item) over the launch's items
+            const uint64_t n_items = nw << (jb - item_bits);
+            const uint64_t grid_waves = kv == 1 ? nw : std::min<uint64_t>(n_items, (uint64_t)ctx->cus * 4 * 8);
+            const unsigned blocks = (unsigned)((grid_waves + 3) / 4);
+            if (kv == 2) {
+                if ((e = launch_zero_words(d_counter, 1, stream)) != hipSuccess) { fail(e, "zero counter"); goto done; }
+                if (listed && (e = launch_zero_words(d_rows, nw * batch * 2, stream)) != hipSuccess) {
+                    fail(e, "zero rows");
+                    goto done;
+                }
+            }
             if (e0 && (e = hipEventRecord(e0, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
             if (kv == 1) {
                 a1.n_waves = nw;
@@ -576,16 +611,24 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
                 a1.chunk_ids = ids;
                 hipLaunchKernelGGL(fn1, dim3(blocks), dim3(256), 0, stream, a1, d_out);
             } else {
-                a2.n_waves = nw;
+                a2.n_chunks = nw;
+                a2.n_items = (uint32_t)n_items;
                 a2.chunk_base = chunk_offset + base;
                 a2.chunk_ids = ids;
-                hipLaunchKernelGGL(fn2, dim3(blocks), dim3(256), 0, stream, a2, d_out);
+                hipLaunchKernelGGL(fn2, dim3(blocks), dim3(256), 0, stream, a2);
             }
             if ((e = hipGetLastError()) != hipSuccess) { fail(e, "kernel launch"); goto done; }
             if (e1 && (e = hipEventRecord(e1, stream)) != hipSuccess) { fail(e, "hipEventRecord"); goto done; }
-            if (listed) {
+            if (listed && kv == 1) {
                 if ((e = hipMemcpyAsync(h_out.data(), d_out, nw * batch * sizeof(double), hipMemcpyDeviceToHost,
                                         stream)) != hipSuccess) { fail(e, "hipMemcpyAsync"); goto done; }
+            }
+            if (listed && kv == 2) {
+                if ((e = hipMemcpyAsync(h_rows.data(), d_rows, nw * batch * 2 * sizeof(unsigned long long),
+                                        hipMemcpyDeviceToHost, stream)) != hipSuccess) {
+                    fail(e, "hipMemcpyAsync");
+                    goto done;
+                }
             }
             if ((e = hipStreamSynchronize(stream)) != hipSuccess) { fail(e, "hipStreamSynchronize"); goto done; }
             if (e0) {
@@ -598,7 +641,13 @@ static sk_status run_sum(const SumRequest& R, std::vector<uint64_t>& out, sk_sta
                 for (uint64_t w = 0; w < nw; ++w)
                     for (int i = 0; i < live; ++i) {
                         const int gi = bt * batch + i;
-                        out[(base + w) * np + gi] = fp_to_residue(h_out[w * batch + i], R.primes[gi]);
+                        if (kv == 1) {
+                            out[(base + w) * np + gi] = fp_to_residue(h_out[w * batch + i], R.primes[gi]);
+                        } else {
+                            const size_t r = 2 * (w * batch + i);
+                            out[(base + w) * np + gi] =
+                                (uint64_t)((((u128)h_rows[r + 1] << 64) | h_rows[r]) % R.primes[gi]);
+                        }
                     }
             }
             terms_done += nw * terms_per_chunk;
@@ -679,7 +728,7 @@ namespace sk {
 // Device workspace of the counting entry points (sk_count_ex, sk_count_part,
 // sk_count_batch): one batched launch's accumulators and counter, which also
 // hold the accumulators of a separate count.
-constexpr size_t kCountWsBytes = kBatchWsBytes > kSumAccBytes ? kBatchWsBytes : kSumAccBytes;
+constexpr size_t kCountWsBytes = kBatchWsBytes > kSumWsBytes ? kBatchWsBytes : kSumWsBytes;
 
 static BatchLaunchFn g_batch_fn[kBatchGroups][2];
 

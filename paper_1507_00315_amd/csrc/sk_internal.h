@@ -73,18 +73,29 @@ struct RevMasks {
     int32_t pad;
 };
 
-// Arguments of one launch of the specialised exact kernel (exact_v2.hip);
+// Arguments of one launch of the specialised exact kernel (exact_v2_body.h);
 // everything about the instance itself is compiled in.
+//
+// The launch is persistent: its waves pull work items from a queue (a device
+// counter, zero before the launch) until the launch's items are exhausted.
+// Item i is 2^item_job_bits consecutive jobs of chunk i >> (job_bits_per_chunk
+// - item_job_bits) of the launch; the launch's chunk c is chunk_ids[c], or
+// chunk_base + c.
 struct ExactArgsV2 {
     RevMasks rev;
     double prime[kMaxPrimes];
     double pinv[kMaxPrimes];
     int32_t job_bits_per_chunk;  // low job variables enumerated inside one chunk
-    int32_t pad0;
-    uint64_t chunk_base;         // chunk index of wave 0 (when chunk_ids == nullptr)
-    const uint64_t* chunk_ids;   // device array, one chunk id per wave, or nullptr
-    uint64_t n_waves;            // waves with work in this launch
-    unsigned long long* acc;     // as ExactArgs::acc
+    int32_t item_job_bits;       // jobs per work item: 2^item_job_bits (<= 2^job_bits_per_chunk)
+    uint64_t chunk_base;         // chunk index of the launch's chunk 0 (when chunk_ids == nullptr)
+    const uint64_t* chunk_ids;   // device array, one chunk id per chunk of the launch, or nullptr
+    uint64_t n_chunks;           // chunks of this launch
+    uint32_t n_items;            // work items of this launch (n_chunks << (jb - item_job_bits))
+    uint32_t pad0;
+    uint32_t* counter;           // device: next work item (0 before the launch)
+    unsigned long long* acc;     // total mode: as ExactArgs::acc
+    unsigned long long* rows;    // row mode (acc == nullptr): n_chunks x P (low word, carries)
+                                 // sums of each chunk's residues in [0, p), zero before the launch
     uint64_t x_extra;            // as ExactArgs::x_extra
 };
 

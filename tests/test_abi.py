@@ -145,11 +145,12 @@ def test_workspace_sizes_are_host_only():
     b = sk.workspace_bytes([(16, "skolem"), (15, "langford"), (14, "hooked", sk.ORDERED)])
     assert a == b and 16 * 4 * 16 <= a <= 4096
     assert sk.workspace_bytes([(40, "skolem")]) == 0
-    # listed chunks: accumulators, then per wave of a launch one row of up to
-    # four fp64 residues and one chunk id, each region rounded to 256 bytes
+    # listed chunks: accumulators and the work-queue counter (256 + 256), then
+    # per chunk of a launch one row of up to four 128-bit sums and one chunk
+    # id, each region rounded to 256 bytes
     t = {"waves_per_launch": 64}
-    assert sk.partial_workspace_bytes(20, "skolem", 1000, 2, t) == 256 + 64 * 32 + 512
-    assert sk.partial_workspace_bytes(20, "skolem", 10, 2, t) == 256 + 512 + 256
+    assert sk.partial_workspace_bytes(20, "skolem", 1000, 2, t) == 512 + 64 * 64 + 512
+    assert sk.partial_workspace_bytes(20, "skolem", 10, 2, t) == 512 + 768 + 256
     assert sk.partial_workspace_bytes(20, "skolem", 10, 9, t) == 0
 
 
