@@ -131,18 +131,19 @@ def valu_per_term(desc) -> int:
     """VALU instructions the tuned kernel issues per sign vector (design count):
     NP packed adds A + B, NQ packed pair products, NQ SDWA quad products, NQ
     conversions to fp64, NQ - G exact group products, the exact high/low split
-    of g0 g1 (G >= 2), and per prime c(G) residue/accumulate instructions
-    (G = 1: 4; G = 2: 4 plus one low-part add shared by all primes; G = 3: 11;
-    each further group: 6 more)."""
+    of g0 g1 (G >= 2), and per prime 4 residue/accumulate instructions (plus
+    one low-part add shared by all primes for G >= 2).  With G >= 3 groups the
+    kernel runs the two-group chain on g0 and the product of the other groups
+    (one more group product, two range checks) and evaluates a job again with
+    the full chain only when a term left that chain's exact range, which the
+    largest products alone do: the count is the two-group one."""
     nq, G, P = desc["quads"], desc["groups"], desc["primes_used"]
     np_ = 2 * nq
     if G == 1:
-        chain = 4 * P
-    elif G == 2:
-        chain = 4 * P + 1
-    else:
-        chain = P * (11 + 6 * (G - 3))
-    return np_ + 3 * nq + (nq - G) + (2 if G >= 2 else 0) + chain
+        return np_ + 3 * nq + (nq - 1) + 4 * P
+    if G == 2:
+        return np_ + 3 * nq + (nq - 2) + 2 + 4 * P + 1
+    return np_ + 3 * nq + (nq - 2) + 2 + 2 + 4 * P + 1
 
 
 def ring_ops_per_term(n: int, P: int) -> int:

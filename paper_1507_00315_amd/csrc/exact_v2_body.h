@@ -315,9 +315,15 @@ struct ExactV2 {
     // two product groups the exact low part l of g0 g1 does not depend on the
     // prime; it is summed once in accl and added to every prime's sum when the
     // block is reduced.
-    template <bool NEG>
+    // FAST (G >= 3): the two-group chain of G = 2 on g0 = group 0 (below
+    // 2^53 by the plan's bound) and g1 = the product of every other group.  It
+    // is exact only while |g1| < 2^53 and |g0 g1| < 2^96, which the plan does
+    // not guarantee; the running maxima of both go to mx, and the caller
+    // evaluates the job again without FAST if they were reached.
+    template <bool NEG, bool FAST = false>
     __device__ static __forceinline__ void term(const uint32_t (&A)[NP], const Uniform& u, const double (&pr)[P],
-                                                const double (&pinv)[P], double (&acc)[P], double& accl)
+                                                const double (&pinv)[P], double (&acc)[P], double& accl,
+                                                double (&mx)[2])
     {
         uint32_t f[NP];
         static_for<0, NP>([&](auto pc) {
@@ -329,6 +335,25 @@ struct ExactV2 {
             constexpr int i = decltype(ic)::value;
             q[i] = (double)mul_halves(pk_mul(f[2 * i], f[2 * i + 1]));
         });
+        if constexpr (FAST) {
+            static_assert(G >= 3, "the fast chain merges groups 1 .. G-1");
+            constexpr int q1 = PL.qb[1];
+            double g0 = q[0];
+            static_for<1, q1>([&](auto jc) { g0 *= q[decltype(jc)::value]; });
+            double g1 = q[q1];
+            static_for<q1 + 1, NQ>([&](auto jc) { g1 *= q[decltype(jc)::value]; });
+            const double h = g0 * g1;
+            const double l = __builtin_fma(g0, g1, -h);
+            mx[0] = __builtin_fmax(mx[0], __builtin_fabs(g1));
+            mx[1] = __builtin_fmax(mx[1], __builtin_fabs(h));
+            static_for<0, P>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                const double s = __builtin_fma(quot_nearest(h, pinv[i]), -pr[i], h);
+                acc[i] = NEG ? acc[i] - s : acc[i] + s;
+            });
+            accl = NEG ? accl - l : accl + l;
+            return;
+        }
         double g[G];
         static_for<0, G>([&](auto gc) {
             constexpr int gi = decltype(gc)::value;
@@ -443,25 +468,44 @@ __device__ __forceinline__ void exact_v2_jobs(uint64_t chunk, int jb, uint64_t j
         const int neg0 = (__builtin_popcountll(u.XU) + lane_parity) & 1;
 
         double acc[P];
+        double mx[2] = {0.0, 0.0};
+        // The walk of the job: 2^W steps in blocks of D.
+        auto walk = [&](auto fast) {
+            constexpr bool FAST = decltype(fast)::value;
 #pragma unroll
-        for (int i = 0; i < P; ++i) acc[i] = 0.0;
-        constexpr uint64_t nblocks = 1ull << (W - (INNER + 1));
-        for (uint64_t ds = 0; ds < nblocks; ++ds) {
-            if (ds > 0) K::template flip_walk_bit<INNER + 1>(u, INNER + 1 + (int)__builtin_ctzll(ds));
-            // |accl| <= D * 2^43 (low parts of products below 2^96)
-            double accl = 0.0;
-            static_for<0, D>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                if constexpr (i > 0) {
-                    if constexpr (K::ctz_ce(i) < INNER) K::template flip_inner<i>(u);
-                    else K::template flip_outer<2 + INNER>(u);
-                }
-                K::template term<(i & 1) != 0>(A, u, pr, pinv, acc, accl);
-            });
-            static_for<0, P>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                acc[i] = reduce_balanced(acc[i] + accl, pr[i], pinv[i]);
-            });
+            for (int i = 0; i < P; ++i) acc[i] = 0.0;
+            constexpr uint64_t nblocks = 1ull << (W - (INNER + 1));
+            for (uint64_t ds = 0; ds < nblocks; ++ds) {
+                if (ds > 0) K::template flip_walk_bit<INNER + 1>(u, INNER + 1 + (int)__builtin_ctzll(ds));
+                // |accl| <= D * 2^43 (low parts of products below 2^96)
+                double accl = 0.0;
+                static_for<0, D>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    if constexpr (i > 0) {
+                        if constexpr (K::ctz_ce(i) < INNER) K::template flip_inner<i>(u);
+                        else K::template flip_outer<2 + INNER>(u);
+                    }
+                    K::template term<(i & 1) != 0, FAST>(A, u, pr, pinv, acc, accl, mx);
+                });
+                static_for<0, P>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    acc[i] = reduce_balanced(acc[i] + accl, pr[i], pinv[i]);
+                });
+            }
+        };
+        if constexpr (K::G >= 3) {
+            walk(std::true_type{});
+            // a term of this job outside the two-group chain's exact range (rare:
+            // the largest products come from nearly periodic sign vectors): the
+            // job again with the full chain
+            const bool out_of_range = mx[0] >= 0x1p53 || mx[1] >= 0x1p96;
+            if (__builtin_amdgcn_ballot_w64(out_of_range) != 0) {
+                u.XU = xu_job;
+                K::init_uniform(u);
+                walk(std::false_type{});
+            }
+        } else {
+            walk(std::false_type{});
         }
         static_for<0, P>([&](auto ic) {
             constexpr int i = decltype(ic)::value;

@@ -10,6 +10,9 @@ benchmark's n = 24 figures and the largest single-GPU counts come from).
   8192-chunk launch the benchmark times) and S(25) (2^28 per chunk, the n = 25
   kernel) against the oracle's recomputation stored by
   tests/golden/make_big_chunks.py.
+* Single jobs of S(24) and L(24) whose products leave the two-group chain's
+  exact range (the kernel evaluates them again with three groups) against the
+  oracle computed in the test.
 """
 import json
 import os
@@ -17,6 +20,7 @@ import sys
 
 import pytest
 
+import oracle as O
 import paper_1507_00315_amd as sk
 from paper_1507_00315_amd import inputs
 
@@ -100,3 +104,41 @@ def test_s25_chunks_match_oracle():
         assert row == [int(x) for x in ch["residues"]], ch["id"]
     ref = sk.partial_chunks(25, "skolem", c["log2_chunks"], ids[:2], primes, tuning={"kernel": 1})
     assert ref == rows[:2]
+
+
+def _product_at_all_plus(n, variant):
+    """|prod_k f_k| (factors with an even pair count halved, as the kernel
+    holds them) at x = +1...+1, where f_k is the number of pairs at d_k."""
+    pos, d = O.instance(n, variant)
+    ps = set(pos)
+    prod = 1
+    for dk in d:
+        L = sum(1 for p in pos if p + dk in ps)
+        prod *= L // 2 if L % 2 == 0 else L
+    return prod
+
+
+@pytest.mark.parametrize("variant", ["skolem", "langford"])
+def test_jobs_outside_the_fast_chain_match_oracle(variant):
+    """Chunks of one job each (2^21 sign vectors; chunk bits = every job
+    variable).  Job 0 holds x = +1...+1, job 0x2AAAAAA the alternating vector,
+    job 0x3FFFFFF the vector with every job variable -1: products above 2^96,
+    beyond the two-group chain, so the kernel must redo these jobs with three
+    groups; the other ids are ordinary jobs.  Every row must equal the oracle's
+    Gray-walk sum over the same sign vectors."""
+    n = 24
+    assert _product_at_all_plus(n, variant) >= 1 << 96  # |f_k| = L_k at both patterns
+    c = sk.max_chunk_bits(n, variant)
+    assert c == 26
+    ids = [0, 0x2AAAAAA, 0x3FFFFFF] + inputs.distinct_ids(2424, c, 3)
+    primes = O.primes_below(1 << 46, 2)
+    _say(f"{variant} 24: {len(ids)} single-job chunks")
+    rows = sk.partial_chunks(n, variant, c, ids, primes)
+    pos, _ = O.instance(n, variant)
+    m = len(pos)
+    for cid, row in zip(ids, rows):
+        fixed = {pos[0]: 1}
+        for b in range(c):
+            fixed[pos[m - 6 - c + b]] = -1 if (cid >> b) & 1 else 1
+        want = [O.chunk_partial(n, variant, fixed, p, "gray", threads=8) for p in primes]
+        assert row == want, (variant, hex(cid))
