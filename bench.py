@@ -78,9 +78,10 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # (kernel, workload or leg, log2 sign vectors per work item, waves per launch):
     #     (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact_batch_kernel", "batch", 22, 6144): ("b7eeb1ea4b6d7862", 1222.9375, 13246.5625),
-    ("exact_v2_kernel", "skolem:24 slice", 26, 8192): ("90787bfd0117604f", 368.4375, 128.0),
-    ("exact_v2_kernel", "langford:24 slice", 26, 8192): ("90787bfd0117604f", 366.0, 128.0),
+    ("exact_batch_kernel", "batch", 22, 6144): ("45bf53824210897b", 1176.6875, 13248.53125),
+    ("exact_batch_kernel", "batch", 22, 8192): ("45bf53824210897b", 1190.4375, 13311.625),
+    ("exact_v2_kernel", "skolem:24 slice", 26, 8192): ("69044c54fbc81476", 642.6875, 24832.0),
+    ("exact_v2_kernel", "langford:24 slice", 26, 8192): ("69044c54fbc81476", 622.625, 24832.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
@@ -234,7 +235,7 @@ def cpu_baseline(instances):
             "backtracking": bt}
 
 
-def config5_ladder():
+def geometric_ladder_49():
     """The 48 geometric replicas 0.05 * 120^(j/47), j = 0..47 (0.05 .. 6),
     below them the beta = 0 level whose samples give Z(beta_1) / Z(0); the
     terminal factor is the fraction of E = 0 samples at beta = 6."""
@@ -271,7 +272,7 @@ def pt_bench(sk, want, plain_iters, learned_iters, tuned_iters, ladders: int, le
     paper's estimates.  Every run first burns in (learned: and trains on) a
     quarter of its recorded iterations; half_z is the equilibration check of
     each run (its two halves against each other)."""
-    fixed = config5_ladder()
+    fixed = geometric_ladder_49()
     runs = []
     tuned = {}
 

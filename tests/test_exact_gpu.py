@@ -58,7 +58,7 @@ def test_reported_counts_at_n1():
     assert sk.count_larsen(1, "skolem", no_shortcut=True).count == 1
 
 
-def test_config1_skolem_12_and_zeros():
+def test_skolem_12_without_symmetries_and_zeros():
     """S(12) over 2^23 sign vectors, two primes; S(10) = S(11) = 0 (Table 7;
     existence, Sec. 1.1)."""
     r = sk.count_ex(12, "skolem", tuning={"primes": 2}, no_symmetry=True)
