@@ -319,7 +319,7 @@ struct ExactV2 {
     // 2^53 by the plan's bound) and g1 = the product of every other group.  It
     // is exact only while |g1| < 2^53 and |g0 g1| < 2^96, which the plan does
     // not guarantee; the running maxima of both go to mx, and the caller
-    // evaluates the job again without FAST if they were reached.
+    // evaluates the segment again without FAST if they were reached.
     template <bool NEG, bool FAST = false>
     __device__ static __forceinline__ void term(const uint32_t (&A)[NP], const Uniform& u, const double (&pr)[P],
                                                 const double (&pinv)[P], double (&acc)[P], double& accl,
@@ -397,6 +397,29 @@ struct ExactV2 {
     }
 };
 
+// A 64-bit value read from the first active lane.  The builtin works on int:
+// each half goes back through uint32_t before widening, so that a low word
+// with bit 31 set is not sign-extended into the high word.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
+{
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
+// A wave-uniform 64-bit value copied into a vector register pair (it keeps no
+// scalar registers while it waits).
+__device__ __forceinline__ uint64_t vgpr_copy(uint64_t x)
+{
+    uint64_t r;
+    asm("v_mov_b64 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
+// Blocks per segment of the two-group chain (G >= 3): 2^6 blocks of 32 steps,
+// 2^17 sign vectors over the wave.
+constexpr uint64_t kFastSegBlocks = 64;
+
 // Jobs [j_begin, j_end) of one chunk (chunk id, 2^jb jobs) evaluated by the
 // calling wavefront and added to acc_tot (per lane, balanced residues: the
 // wave's sum is the sum over the lanes).  x_extra: bits ORed into every job's
@@ -469,13 +492,11 @@ __device__ __forceinline__ void exact_v2_jobs(uint64_t chunk, int jb, uint64_t j
 
         double acc[P];
         double mx[2] = {0.0, 0.0};
-        // The walk of the job: 2^W steps in blocks of D.
-        auto walk = [&](auto fast) {
+        // Blocks [b0, b1) of the walk of the job: D steps each, the step between
+        // blocks flipping the walked variable of the block index's lowest set bit.
+        auto walk = [&](auto fast, uint64_t b0, uint64_t b1) {
             constexpr bool FAST = decltype(fast)::value;
-#pragma unroll
-            for (int i = 0; i < P; ++i) acc[i] = 0.0;
-            constexpr uint64_t nblocks = 1ull << (W - (INNER + 1));
-            for (uint64_t ds = 0; ds < nblocks; ++ds) {
+            for (uint64_t ds = b0; ds < b1; ++ds) {
                 if (ds > 0) K::template flip_walk_bit<INNER + 1>(u, INNER + 1 + (int)__builtin_ctzll(ds));
                 // |accl| <= D * 2^43 (low parts of products below 2^96)
                 double accl = 0.0;
@@ -493,25 +514,47 @@ __device__ __forceinline__ void exact_v2_jobs(uint64_t chunk, int jb, uint64_t j
                 });
             }
         };
+        // the job's weight (Lemma 2.3) and sign, applied to each part of its sum
+        auto add_to_total = [&]() {
+            static_for<0, P>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                const double aw = w == 2 ? acc[i] + acc[i] : acc[i];  // |aw| <= 1.5 p
+                acc_tot[i] = reduce_balanced(neg0 ? acc_tot[i] - aw : acc_tot[i] + aw, pr[i], pinv[i]);
+            });
+        };
+        constexpr uint64_t nblocks = 1ull << (W - (INNER + 1));
         if constexpr (K::G >= 3) {
-            walk(std::true_type{});
-            // a term of this job outside the two-group chain's exact range (rare:
-            // the largest products come from nearly periodic sign vectors): the
-            // job again with the full chain
-            const bool out_of_range = mx[0] >= 0x1p53 || mx[1] >= 0x1p96;
-            if (__builtin_amdgcn_ballot_w64(out_of_range) != 0) {
-                u.XU = xu_job;
-                K::init_uniform(u);
-                walk(std::false_type{});
+            // Segments of kFastSegBlocks blocks with the two-group chain.  A
+            // segment in which some term left that chain's exact range (rare:
+            // the largest products come from nearly periodic sign vectors) is
+            // evaluated again with the full chain, from its first sign vector:
+            // the scalar state is a function of the sign mask alone, so the
+            // mask at the segment's start (kept in a vector register) restores
+            // it.  Each segment's sum goes to the total once it is final.
+            constexpr uint64_t seg = nblocks < kFastSegBlocks ? nblocks : kFastSegBlocks;
+            for (uint64_t s0 = 0; s0 < nblocks; s0 += seg) {
+                const uint64_t xu_seg = vgpr_copy(u.XU);
+#pragma unroll
+                for (int i = 0; i < P; ++i) acc[i] = 0.0;
+                mx[0] = 0.0;
+                mx[1] = 0.0;
+                walk(std::true_type{}, s0, s0 + seg);
+                const bool out_of_range = mx[0] >= 0x1p53 || mx[1] >= 0x1p96;
+                if (__builtin_amdgcn_ballot_w64(out_of_range) != 0) {
+                    u.XU = uniform_u64(xu_seg);
+                    K::init_uniform(u);
+#pragma unroll
+                    for (int i = 0; i < P; ++i) acc[i] = 0.0;
+                    walk(std::false_type{}, s0, s0 + seg);
+                }
+                add_to_total();
             }
         } else {
-            walk(std::false_type{});
+#pragma unroll
+            for (int i = 0; i < P; ++i) acc[i] = 0.0;
+            walk(std::false_type{}, 0, nblocks);
+            add_to_total();
         }
-        static_for<0, P>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            const double aw = w == 2 ? acc[i] + acc[i] : acc[i];  // |aw| <= 1.5 p
-            acc_tot[i] = reduce_balanced(neg0 ? acc_tot[i] - aw : acc_tot[i] + aw, pr[i], pinv[i]);
-        });
     }
 }
 
@@ -540,11 +583,6 @@ __device__ __forceinline__ double in_vgpr(double x)
     return r;
 }
 
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
-{
-    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
-           (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
-}
 
 // Persistent launch: every wave pulls work items (2^item_job_bits jobs of one
 // chunk) from the launch's queue until it is empty.  Total mode (acc): each

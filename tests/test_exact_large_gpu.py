@@ -12,7 +12,8 @@ benchmark's n = 24 figures and the largest single-GPU counts come from).
   tests/golden/make_big_chunks.py.
 * Single jobs of S(24) and L(24) whose products leave the two-group chain's
   exact range (the kernel evaluates them again with three groups) against the
-  oracle computed in the test.
+  oracle computed in the test; chunks of L(30) with ids of 33 bits (four
+  product groups) likewise.
 """
 import json
 import os
@@ -123,8 +124,8 @@ def test_jobs_outside_the_fast_chain_match_oracle(variant):
     """Chunks of one job each (2^21 sign vectors; chunk bits = every job
     variable).  Job 0 holds x = +1...+1, job 0x2AAAAAA the alternating vector,
     job 0x3FFFFFF the vector with every job variable -1: products above 2^96,
-    beyond the two-group chain, so the kernel must redo these jobs with three
-    groups; the other ids are ordinary jobs.  Every row must equal the oracle's
+    beyond the two-group chain, so the kernel must redo the segments that
+    hold them with three groups; the other ids are ordinary jobs.  Every row must equal the oracle's
     Gray-walk sum over the same sign vectors."""
     n = 24
     assert _product_at_all_plus(n, variant) >= 1 << 96  # |f_k| = L_k at both patterns
@@ -142,3 +143,26 @@ def test_jobs_outside_the_fast_chain_match_oracle(variant):
             fixed[pos[m - 6 - c + b]] = -1 if (cid >> b) & 1 else 1
         want = [O.chunk_partial(n, variant, fixed, p, "gray", threads=8) for p in primes]
         assert row == want, (variant, hex(cid))
+
+
+def test_chunk_ids_above_32_bits_match_oracle():
+    """Langford n = 30 with its 33 chunk variables (chunks of 2^26 sign
+    vectors): chunk ids with bit 31 and bit 32 set (the wave reads an id as two
+    32-bit halves), four product groups merged into two by the fast chain.
+    Ids: every chunk variable -1 (products near the maximum, reached in a
+    segment in the middle of the walk), bit 31 alone, the alternating
+    pattern, and two seeded ids with bit 32 set."""
+    n, variant, c = 30, "langford", 33
+    assert sk.max_chunk_bits(n, variant) == c
+    ids = [(1 << c) - 1, 1 << 31, 0x155555555] + [x | (1 << 32) for x in inputs.distinct_ids(3030, 31, 2)]
+    primes = O.primes_below(1 << 46, 3)
+    _say(f"{variant} {n}: {len(ids)} chunks of 2^26 sign vectors, ids up to 33 bits")
+    rows = sk.partial_chunks(n, variant, c, ids, primes)
+    pos, _ = O.instance(n, variant)
+    m = len(pos)
+    for cid, row in zip(ids, rows):
+        fixed = {pos[0]: 1}
+        for b in range(c):
+            fixed[pos[m - 6 - c + b]] = -1 if (cid >> b) & 1 else 1
+        want = [O.chunk_partial(n, variant, fixed, p, "gray", threads=8) for p in primes]
+        assert row == want, (variant, n, hex(cid))
