@@ -78,10 +78,10 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # (kernel, workload or leg, log2 sign vectors per work item, waves per launch):
     #     (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact_batch_kernel", "batch", 22, 6144): ("45bf53824210897b", 1176.6875, 13248.53125),
-    ("exact_batch_kernel", "batch", 22, 8192): ("45bf53824210897b", 1190.4375, 13311.625),
-    ("exact_v2_kernel", "skolem:24 slice", 26, 8192): ("69044c54fbc81476", 642.6875, 24832.0),
-    ("exact_v2_kernel", "langford:24 slice", 26, 8192): ("69044c54fbc81476", 622.625, 24832.0),
+    ("exact_batch_kernel", "batch", 22, 6144): ("5ddfd7c189f85e45", 1193.1875, 13245.125),
+    ("exact_batch_kernel", "batch", 22, 8192): ("5ddfd7c189f85e45", 1207.0625, 13309.3125),
+    ("exact_v2_kernel", "skolem:24 slice", 26, 8192): ("91f077f1cff2861c", 639.5, 24832.0),
+    ("exact_v2_kernel", "langford:24 slice", 26, 8192): ("91f077f1cff2861c", 631.5625, 24832.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
