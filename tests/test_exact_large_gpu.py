@@ -119,30 +119,31 @@ def _product_at_all_plus(n, variant):
     return prod
 
 
-@pytest.mark.parametrize("variant", ["skolem", "langford"])
-def test_jobs_outside_the_fast_chain_match_oracle(variant):
-    """Chunks of one job each (2^21 sign vectors; chunk bits = every job
-    variable).  Job 0 holds x = +1...+1, job 0x2AAAAAA the alternating vector,
-    job 0x3FFFFFF the vector with every job variable -1: products above 2^96,
-    beyond the two-group chain, so the kernel must redo the segments that
-    hold them with three groups; the other ids are ordinary jobs.  Every row must equal the oracle's
-    Gray-walk sum over the same sign vectors."""
-    n = 24
+@pytest.mark.parametrize("variant,n", [("skolem", 24), ("langford", 24), ("hooked", 23)])
+def test_jobs_outside_the_fast_chain_match_oracle(variant, n):
+    """Chunks of one job each (chunk bits = every job variable).  Three jobs
+    hold nearly periodic sign vectors whose products exceed 2^96, beyond the
+    two-group chain, so the kernel must redo the segments that hold them with
+    the full chain: every job variable +1 (x = +1...+1 lies in it), the job
+    variables alternating as in x_p = (-1)^(p+1) (the alternating vector), and
+    every job variable -1.  Three seeded ids are ordinary jobs.  Every row must
+    equal the oracle's Gray-walk sum over the same sign vectors."""
     assert _product_at_all_plus(n, variant) >= 1 << 96  # |f_k| = L_k at both patterns
     c = sk.max_chunk_bits(n, variant)
-    assert c == 26
-    ids = [0, 0x2AAAAAA, 0x3FFFFFF] + inputs.distinct_ids(2424, c, 3)
-    primes = O.primes_below(1 << 46, 2)
-    _say(f"{variant} 24: {len(ids)} single-job chunks")
-    rows = sk.partial_chunks(n, variant, c, ids, primes)
     pos, _ = O.instance(n, variant)
     m = len(pos)
+    job_pos = [pos[m - 6 - c + b] for b in range(c)]
+    alternating = sum(1 << b for b, p in enumerate(job_pos) if p % 2 == 0)
+    ids = [0, alternating, (1 << c) - 1] + inputs.distinct_ids(2424, c, 3)
+    primes = O.primes_below(1 << 46, 2)
+    _say(f"{variant} {n}: {len(ids)} single-job chunks of {c} chunk bits")
+    rows = sk.partial_chunks(n, variant, c, ids, primes)
     for cid, row in zip(ids, rows):
         fixed = {pos[0]: 1}
         for b in range(c):
-            fixed[pos[m - 6 - c + b]] = -1 if (cid >> b) & 1 else 1
+            fixed[job_pos[b]] = -1 if (cid >> b) & 1 else 1
         want = [O.chunk_partial(n, variant, fixed, p, "gray", threads=8) for p in primes]
-        assert row == want, (variant, hex(cid))
+        assert row == want, (variant, n, hex(cid))
 
 
 def test_chunk_ids_above_32_bits_match_oracle():
