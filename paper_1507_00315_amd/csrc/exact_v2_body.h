@@ -529,11 +529,14 @@ __device__ __forceinline__ void exact_v2_jobs(uint64_t chunk, int jb, uint64_t j
             // the largest products come from nearly periodic sign vectors) is
             // evaluated again with the full chain, from its first sign vector:
             // the scalar state is a function of the sign mask alone, so the
-            // mask at the segment's start (kept in a vector register) restores
-            // it.  Each segment's sum goes to the total once it is final.
+            // mask at the segment's start (kept in the wave's LDS slot, which
+            // costs no register) restores it.  Each segment's sum goes to the
+            // total once it is final.
             constexpr uint64_t seg = nblocks < kFastSegBlocks ? nblocks : kFastSegBlocks;
+            __shared__ uint64_t seg_mask[4];  // one slot per wave of the workgroup
+            const int wslot = (int)(threadIdx.x >> 6) & 3;
             for (uint64_t s0 = 0; s0 < nblocks; s0 += seg) {
-                const uint64_t xu_seg = vgpr_copy(u.XU);
+                if (lane == 0) seg_mask[wslot] = u.XU;
 #pragma unroll
                 for (int i = 0; i < P; ++i) acc[i] = 0.0;
                 mx[0] = 0.0;
@@ -541,7 +544,7 @@ __device__ __forceinline__ void exact_v2_jobs(uint64_t chunk, int jb, uint64_t j
                 walk(std::true_type{}, s0, s0 + seg);
                 const bool out_of_range = mx[0] >= 0x1p53 || mx[1] >= 0x1p96;
                 if (__builtin_amdgcn_ballot_w64(out_of_range) != 0) {
-                    u.XU = uniform_u64(xu_seg);
+                    u.XU = uniform_u64(seg_mask[wslot]);
                     K::init_uniform(u);
 #pragma unroll
                     for (int i = 0; i < P; ++i) acc[i] = 0.0;
