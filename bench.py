@@ -78,10 +78,10 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # (kernel, workload or leg, log2 sign vectors per work item, waves per launch):
     #     (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact_batch_kernel", "batch", 22, 6144): ("5ddfd7c189f85e45", 1193.1875, 13245.125),
-    ("exact_batch_kernel", "batch", 22, 8192): ("5ddfd7c189f85e45", 1207.0625, 13309.3125),
-    ("exact_v2_kernel", "skolem:24 slice", 26, 8192): ("91f077f1cff2861c", 639.5, 24832.0),
-    ("exact_v2_kernel", "langford:24 slice", 26, 8192): ("91f077f1cff2861c", 631.5625, 24832.0),
+    ("exact_batch_kernel", "batch", 22, 6144): ("f9b7678e068e1eee", 1212.4375, 13248.40625),
+    ("exact_batch_kernel", "batch", 22, 8192): ("f9b7678e068e1eee", 1177.125, 13311.875),
+    ("exact_v2_kernel", "skolem:24 slice", 26, 8192): ("1852f1df76b2ad87", 628.4375, 24832.0),
+    ("exact_v2_kernel", "langford:24 slice", 26, 8192): ("1852f1df76b2ad87", 629.75, 24832.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
