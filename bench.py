@@ -68,8 +68,9 @@ L28_CHUNK_BITS, L28_SLICE = 24, 4096
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs (KiB per
 # dispatch), scaled by what the same counters read for a plain 1 GiB device copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources they
-# were taken on: the fingerprint is a SHA-256 over those sources, and a changed
-# kernel reports traffic null until the counters are taken again.
+# were taken on: the fingerprint is a SHA-256 over those sources with comments
+# removed, and a changed kernel reports traffic null until the counters are
+# taken again.
 KERNEL_SOURCES = {
     "exact_batch_kernel": ["exact_batch.hip", "sk_batch.h", "exact_v2_body.h", "exact_common.h", "sk_plan.h",
                            "sk_internal.h"],
@@ -78,20 +79,27 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # (kernel, workload or leg, log2 sign vectors per work item, waves per launch):
     #     (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact_batch_kernel", "batch", 22, 6144): ("f9b7678e068e1eee", 1212.4375, 13248.40625),
-    ("exact_batch_kernel", "batch", 22, 8192): ("f9b7678e068e1eee", 1177.125, 13311.875),
-    ("exact_v2_kernel", "skolem:24 slice", 26, 8192): ("1852f1df76b2ad87", 628.4375, 24832.0),
-    ("exact_v2_kernel", "langford:24 slice", 26, 8192): ("1852f1df76b2ad87", 629.75, 24832.0),
+    ("exact_batch_kernel", "batch", 22, 6144): ("a8911f1a8df728c6", 1212.4375, 13248.40625),
+    ("exact_batch_kernel", "batch", 22, 8192): ("a8911f1a8df728c6", 1177.125, 13311.875),
+    ("exact_v2_kernel", "skolem:24 slice", 26, 8192): ("b6e4ddcc432bdf6b", 628.4375, 24832.0),
+    ("exact_v2_kernel", "langford:24 slice", 26, 8192): ("b6e4ddcc432bdf6b", 629.75, 24832.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
 def kernel_fingerprint(kernel: str) -> str:
+    """SHA-256 over the kernel's sources with comments removed and white space
+    collapsed (a change of a comment or of layout does not change the kernel;
+    any change of code does)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES.get(kernel, []):
-        with open(os.path.join(ROOT, "paper_1507_00315_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1507_00315_amd", "csrc", name), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -31,6 +31,13 @@
 //     one 24-bit multiply per quad reading both halves (SDWA), conversion to
 //     fp64, exact fp64 group products, then the fp64 residue chain of
 //     exact_common.h per prime.
+//   * Where the plan needs three or more product groups (n >= 22), the walk
+//     runs the cheaper two-group chain on the first group and the product of
+//     the others, keeps per-lane maxima of the two values whose range makes
+//     that chain exact, and evaluates a segment of 2^11 steps again with the
+//     full chain when a lane of the wave went beyond it.
+//   * Launches are persistent: waves pull work items (a few jobs of one
+//     chunk) from a device counter until the launch's items run out.
 //
 // LARSEN = true evaluates the inclusion-exclusion sum of Sec. 2 (the third
 // counting approach) with the same machinery: the variables are y in {0, 1}
