@@ -34,7 +34,7 @@
 //   * Where the plan needs three or more product groups (n >= 22), the walk
 //     runs the cheaper two-group chain on the first group and the product of
 //     the others, keeps per-lane maxima of the two values whose range makes
-//     that chain exact, and evaluates a segment of 2^11 steps again with the
+//     that chain exact, and evaluates a segment of 2^9 steps again with the
 //     full chain when a lane of the wave went beyond it.
 //   * Launches are persistent: waves pull work items (a few jobs of one
 //     chunk) from a device counter until the launch's items run out.
@@ -423,9 +423,10 @@ __device__ __forceinline__ uint64_t vgpr_copy(uint64_t x)
     return r;
 }
 
-// Blocks per segment of the two-group chain (G >= 3): 2^6 blocks of 32 steps,
-// 2^17 sign vectors over the wave.
-constexpr uint64_t kFastSegBlocks = 64;
+// Blocks per segment of the two-group chain (G >= 3): 2^4 blocks of 32 steps,
+// 2^15 sign vectors over the wave (64 blocks: the L(28) slice 3.5 % slower,
+// n = 24 the same).
+constexpr uint64_t kFastSegBlocks = 16;
 
 // Jobs [j_begin, j_end) of one chunk (chunk id, 2^jb jobs) evaluated by the
 // calling wavefront and added to acc_tot (per lane, balanced residues: the
