@@ -33,6 +33,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -389,7 +390,14 @@ def main():
     ap.add_argument("--pt-learned-first", type=int, default=36)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (reference for the HBM byte counters)")
+    ap.add_argument("--issue-calibration", action="store_true",
+                    help="only run the vector-instruction issue-rate program (cost model of the tempering kernel)")
     args = ap.parse_args()
+    if args.issue_calibration:
+        probe = os.path.join(ROOT, "paper_1507_00315_amd", "issue_probe")
+        if not os.path.exists(probe):
+            sys.exit("bench.py: issue_probe is not built (python -m paper_1507_00315_amd.build)")
+        sys.exit(subprocess.call([probe]))
     if args.copy_calibration:
         import torch
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)

@@ -18,6 +18,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libskolem.so")
+# The issue-rate calibration program (not part of the library): the cost
+# model of the tempering kernel, run by `bench.py --issue-calibration`.
+PROBE = os.path.join(HERE, "issue_probe")
 
 SOURCES = ["host.cpp", "pt_host.cpp", "mlp_host.cpp", "exact_v1.hip", "pt.hip", "mlp.hip"]
 
@@ -78,6 +81,10 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         procs.append((oname, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
         while sum(1 for _, p in procs if p.poll() is None) >= jobs:
             time.sleep(0.2)
+    probe_cmd = [hipcc()] + HIPCC_FLAGS + ["-o", PROBE + ".tmp", os.path.join(CSRC, "issue_probe.hip")]
+    if verbose:
+        print(" ".join(probe_cmd), flush=True)
+    procs.append(("issue_probe.hip", subprocess.Popen(probe_cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     errors = []
     for src, p in procs:
         out, _ = p.communicate()
@@ -89,6 +96,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
             print(text)
     if errors:
         raise RuntimeError("hipcc failed:\n" + "\n".join(errors))
+    os.replace(PROBE + ".tmp", PROBE)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     subprocess.check_call(cmd)

@@ -22,6 +22,14 @@
 // floor(2^32 exp(-b e)) computed on the host, so the decisions are bit-exact
 // reproducible.  Initial configurations use counters (0xFFFFFFF0 + block,
 // 0xFFFFFFFF, ladder, level).
+//
+// Cost model: with 1024 ladders there is one wave on each SIMD, and one wave
+// issues about one instruction per five cycles whatever the instruction; the
+// loop is written for the fewest instructions per iteration: the two 32-bit
+// products of a Philox round as single 64-bit multiplies, the exchange test
+// and the upper/lower roles as wave-uniform lane masks on the scalar unit,
+// lane shifts without copies, slots addressed by their LDS address, and the
+// loop and pair-parity bookkeeping on the scalar unit.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -44,14 +52,16 @@ __device__ __forceinline__ int placement(int n, int d, int idx)
 
 // The value held by lane + 1 / lane - 1 (wavefront shifts by one lane, DPP;
 // every lane is active where these are used).  At the ends of the wavefront
-// the lane keeps its own value, which the callers never use.
+// the lane reads 0 (bound control), which the callers never use and which
+// keeps every index formed from it in range; a shift that writes every lane
+// needs no copy of the old value.
 __device__ __forceinline__ int from_lane_above(int x)
 {
-    return __builtin_amdgcn_update_dpp(x, x, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(x, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
 }
 __device__ __forceinline__ int from_lane_below(int x)
 {
-    return __builtin_amdgcn_update_dpp(x, x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(x, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
 }
 
 template <int V>
@@ -66,6 +76,14 @@ __device__ __forceinline__ int placements_of(int n, int d)
     return 2 * n - d - (V == 2 && d == 1);
 }
 
+// A byte of LDS addressed by its 32-bit LDS address.
+typedef __attribute__((address_space(3))) uint8_t lds_byte;
+
+__device__ __forceinline__ lds_byte* lds_at(int addr)
+{
+    return (lds_byte*)(uintptr_t)(uint32_t)addr;
+}
+
 template <int V>
 __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
 {
@@ -77,7 +95,6 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     const int top = a.top;
     const int H = top + 1;
     const int slot_bytes = a.slot_bytes;  // n placements + (top + 1) occupancies, rounded to 4
-    uint8_t* slots = lds;
     uint32_t* hist = (uint32_t*)(lds + (size_t)64 * slot_bytes);  // M x H
     uint32_t* swap_thr = hist + M * H;                              // M x H, copy of a.swap_thr
     const bool live = lane < M;
@@ -92,18 +109,32 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     // branch.  Those lanes never take part in an exchange (so their slots stay
     // their own), their histogram increments are 0 and go to row 0, and their
     // results are never written out.
-    int sb = lane * slot_bytes;  // LDS byte offset of the lane's current slot
+    // LDS address of the lane's current slot (the address itself, not an
+    // offset from the array, so that the slot moves between lanes as a plain
+    // value and its bytes are addressed without an add per access)
+    int sb = (int)(uint32_t)(uintptr_t)(lds_byte*)lds + lane * slot_bytes;
     int E = 0;
-    uint32_t mv_acc = 0, sw_acc = 0;
+    // accepted moves; accepted exchanges counted at the upper level of the
+    // pair (a lane mask the scalar unit forms), moved to the lower level
+    // after the loop
+    uint32_t mv_acc = 0, up_acc = 0;
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     const uint32_t T1 = live ? a.move_thr[lane * 2 + 0] : 0u;
     const uint32_t T2 = live ? a.move_thr[lane * 2 + 1] : 0u;
     const uint32_t hinc = live ? 1u : 0u;
+    // (the two thresholds are in registers before the loop starts, so that
+    // the loop holds no wait for their loads)
+    asm volatile("" ::"v"(T1), "v"(T2));
     uint32_t* const hrow = hist + (live ? lane * H : 0);
     const uint32_t* const trow = swap_thr + (live ? lane * H : 0);
+    // The lanes that are the lower level of an exchange pair, one lane mask
+    // per parity of the iteration (wave-uniform, so the exchange's lane logic
+    // runs on the scalar unit): lane j with j + 1 < M and j of that parity.
+    uint64_t lower_mask[2] = {0, 0};
+    for (int j = 0; j + 1 < M; ++j) lower_mask[j & 1] |= 1ull << j;
     {
-        uint8_t* s = slots + sb;
-        uint8_t* occ = s + n;
+        lds_byte* s = lds_at(sb);
+        lds_byte* occ = s + n;
         for (int p = 0; p <= top; ++p) occ[p] = 0;
         if (live && a.state_in) {
             const uint8_t* src = a.state_in + ((size_t)ladder * M + lane) * n;
@@ -144,11 +175,20 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     philox4x32_10((uint32_t)(a.it_begin + 1), (uint32_t)((a.it_begin + 1) >> 32), ladder, (uint32_t)lane, k0, k1,
                   rn);
     int k = (int)__umulhi(r[0], (uint32_t)n);
-    int a_old = slots[sb + k];
-    for (uint64_t it = a.it_begin; it < a.it_end; ++it) {
+    int a_old = *lds_at(sb + k);
+    // (an opaque start value for a_old: without it the compiler treats the
+    // loop's a_old as a byte, and the iteration takes one instruction more)
+    asm("" : "+v"(a_old));
+    // The loop runs over the counter of the block that the iteration draws
+    // (it + 2), tested for equality, which the scalar unit does on 64 bits;
+    // the lower lanes of the iteration's exchange pairs alternate by an XOR.
+    const uint64_t it_end = a.it_end > a.it_begin ? a.it_end : a.it_begin;
+    uint64_t lower = lower_mask[a.it_begin & 1];
+    const uint64_t lower_flip = lower_mask[0] ^ lower_mask[1];
+    for (uint64_t ic = a.it_begin + 2; ic != it_end + 2; ++ic) {
         // 1. move (pair k, whose current left position a_old was read ahead)
-        uint8_t* s = slots + sb;
-        uint8_t* occ = s + n;
+        lds_byte* s = lds_at(sb);
+        lds_byte* occ = s + n;
         const int d = pair_diff<V>(k);
         const int idx = (int)__umulhi(r[1], (uint32_t)placements_of<V>(n, d));
         const int a_new = placement<V>(n, d, idx);
@@ -160,7 +200,7 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
         // 2. record the energy before the move (LDS atomic add, no read-back;
         // each level owns its row); issued behind the reads it does not feed
         atomicAdd(&hrow[E], hinc);
-        uint32_t c[4] = {(uint32_t)(it + 2), (uint32_t)((it + 2) >> 32), ladder, (uint32_t)lane};
+        uint32_t c[4] = {(uint32_t)ic, (uint32_t)(ic >> 32), ladder, (uint32_t)lane};
         __builtin_amdgcn_sched_barrier(0);
         philox4x32_rounds<0, 5>(c, k0, k1);
         __builtin_amdgcn_sched_barrier(0);
@@ -183,35 +223,48 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
         // is read for every lane (index clamped at 0, where it is not needed),
         // and the next move's s[k] for the three candidate slots (after the
         // writes above, so they see this move)
-        const int parity = (int)(it & 1);
         const int E_up = from_lane_above(E);
         const int sb_up = from_lane_above(sb);
         const int sb_dn = from_lane_below(sb);
         const int dx = E - E_up;
         const uint32_t thr = trow[dx > 0 ? dx : 0];
         const int k_next = (int)__umulhi(rn[0], (uint32_t)n);
-        const int v_own = slots[sb + k_next];
-        const int v_up = slots[sb_up + k_next];
-        const int v_dn = slots[sb_dn + k_next];
+        const int v_own = *lds_at(sb + k_next);
+        const int v_up = *lds_at(sb_up + k_next);
+        const int v_dn = *lds_at(sb_dn + k_next);
         __builtin_amdgcn_sched_barrier(0);
         philox4x32_rounds<5, 10>(c, k0, k1);
         __builtin_amdgcn_sched_barrier(0);
-        const bool lower = (lane + 1 < M) & ((lane & 1) == parity);
-        const bool sw = lower & ((dx <= 0) | (r[3] < thr));
-        const int sw_from_below = from_lane_below((int)sw);
+        // the exchange test as lane masks: the lower lanes of this parity whose
+        // energy does not rise or whose word is under the threshold
+        const uint64_t sw_mask = lower & (__builtin_amdgcn_ballot_w64(dx <= 0) |
+                                                       __builtin_amdgcn_ballot_w64(r[3] < thr));
+        const bool sw = __builtin_amdgcn_inverse_ballot_w64(sw_mask);
+        // the upper level of an accepted exchange: the lane above a lane with
+        // sw set (the mask shifted by one lane)
+        const uint64_t up_mask = sw_mask << 1;
+        const bool upper = __builtin_amdgcn_inverse_ballot_w64(up_mask);
         const int E_dn = from_lane_below(E);
-        const bool upper = (lane >= 1) & (lane < M) & (((lane - 1) & 1) == parity) & (sw_from_below != 0);
         E = sw ? E_up : (upper ? E_dn : E);
         sb = sw ? sb_up : (upper ? sb_dn : sb);
         a_old = sw ? v_up : (upper ? v_dn : v_own);
-        sw_acc += sw ? 1u : 0u;
+        {
+            // up_acc += upper, the mask as the carry-in of one add
+            uint64_t carry_out;
+            asm("v_addc_co_u32_e64 %0, %1, 0, %0, %2" : "+v"(up_acc), "=s"(carry_out) : "s"(up_mask));
+        }
         k = k_next;
+        lower ^= lower_flip;
+        // (keeps the block counter the loop's own variable, so that it is not
+        // recomputed from the iteration number at every step)
+        asm("" : "+s"(ic));
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             r[i] = rn[i];
             rn[i] = c[i];
         }
     }
+    const uint32_t sw_acc = (uint32_t)from_lane_above((int)up_acc);
     __syncthreads();
 
     // outputs: histograms, acceptance counts, states in level order
@@ -220,7 +273,7 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
         a.move_acc[(size_t)ladder * M + lane] += mv_acc;
         a.swap_acc[(size_t)ladder * M + lane] += sw_acc;
         a.energy_out[(size_t)ladder * M + lane] = E;
-        const uint8_t* s = slots + sb;
+        const lds_byte* s = lds_at(sb);
         uint8_t* dst = a.state_out + ((size_t)ladder * M + lane) * n;
         for (int k = 0; k < n; ++k) dst[k] = s[k];
     }

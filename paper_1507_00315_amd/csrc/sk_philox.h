@@ -19,10 +19,12 @@ __device__ __forceinline__ void philox4x32_rounds(uint32_t (&c)[4], uint32_t k0,
     for (int r = R0; r < R1; ++r) {
         const uint32_t kr0 = k0 + (uint32_t)r * 0x9E3779B9u;
         const uint32_t kr1 = k1 + (uint32_t)r * 0xBB67AE85u;
-        const uint32_t lo0 = 0xD2511F53u * c[0];
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
-        const uint32_t lo1 = 0xCD9E8D57u * c[2];
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        // each 32x32->64 product as one 64-bit multiply (one v_mad_u64_u32
+        // on the vector unit instead of a v_mul_lo_u32 and a v_mul_hi_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         // three-input XOR in one instruction (v_bitop3_b32, truth table 0x96);
         // rounds 0 and 1 keep plain XORs, whose operands are often wave-uniform
         // (counter words shared by the wave), so they stay on the scalar unit
