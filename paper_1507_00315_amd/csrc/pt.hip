@@ -28,8 +28,11 @@
 // loop is written for the fewest instructions per iteration: the two 32-bit
 // products of a Philox round as single 64-bit multiplies, the exchange test
 // and the upper/lower roles as wave-uniform lane masks on the scalar unit,
-// lane shifts without copies, slots addressed by their LDS address, and the
-// loop and pair-parity bookkeeping on the scalar unit.
+// lane shifts without copies, slots addressed by their LDS address, the slot
+// address and the energy packed in one register, positions stored less one,
+// Philox blocks split across the iteration boundary, the wave-uniform part of
+// their first rounds drawn 64 blocks at a time, and the loop and pair-parity
+// bookkeeping on the scalar unit.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -38,16 +41,17 @@
 
 namespace sk {
 
-// Placement index -> left position of pair k (1-based), for the variant's
-// position set (V: 0 Skolem, 1 Langford, 2 hooked; a compile-time constant, so
-// the hooked case costs the other two nothing).  Hooked: positions 1..2n-1 and
-// 2n+1; the first 2n-1-d placements end at or below 2n-1, the last one ends at
-// 2n+1.
+// Placement index -> left position of pair k, stored less one (positions
+// 1..2n as 0..2n-1, so that a placement index is its own position), for the
+// variant's position set (V: 0 Skolem, 1 Langford, 2 hooked; a compile-time
+// constant, so the hooked case costs the other two nothing).  Hooked:
+// positions 1..2n-1 and 2n+1; the first 2n-1-d placements end at or below
+// 2n-1, the last one ends at 2n+1.
 template <int V>
 __device__ __forceinline__ int placement(int n, int d, int idx)
 {
-    if constexpr (V == 2) return idx >= 2 * n - 1 - d ? 2 * n + 1 - d : 1 + idx;
-    return 1 + idx;
+    if constexpr (V == 2) return idx >= 2 * n - 1 - d ? 2 * n - d : idx;
+    return idx;
 }
 
 // The value held by lane + 1 / lane - 1 (wavefront shifts by one lane, DPP;
@@ -138,7 +142,7 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
         for (int p = 0; p <= top; ++p) occ[p] = 0;
         if (live && a.state_in) {
             const uint8_t* src = a.state_in + ((size_t)ladder * M + lane) * n;
-            for (int k = 0; k < n; ++k) s[k] = src[k];
+            for (int k = 0; k < n; ++k) s[k] = (uint8_t)(src[k] - 1);
         } else {
             for (int blk = 0; blk * 4 < n; ++blk) {
                 uint32_t r[4];
@@ -156,24 +160,27 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
             occ[s[k]]++;
             occ[s[k] + d]++;
         }
-        for (int p = 1; p <= top; ++p)
-            if (!(V == 2 && p == 2 * n) && occ[p] == 0) ++E;  // the hooked set has no position 2n
+        for (int p = 0; p < top; ++p)  // (position p + 1; the hooked set has no position 2n)
+            if (!(V == 2 && p == 2 * n - 1) && occ[p] == 0) ++E;
     }
     __syncthreads();
 
-    // Software pipeline.  The Philox words are drawn two iterations ahead:
-    // iteration it holds the words of it (r) and it + 1 (rn) and draws those
-    // of it + 2, in two pieces that fill the waits for the iteration's two
-    // dependent LDS round trips (the four occupancies; the exchange threshold).
-    // The byte s[k] that the next move starts from is read in the second round
-    // trip, for each of the three slots the lane can hold after the exchange
-    // (its own, the one above, the one below), and picked once the exchange is
-    // decided.  The scheduling barriers keep each piece of Philox arithmetic
-    // between a read and the first use of its value.
-    uint32_t r[4], rn[4];
+    // Software pipeline.  Each Philox block is drawn in two halves of five
+    // rounds that fill the waits for the two dependent LDS round trips of an
+    // iteration (the four occupancies; the exchange threshold): iteration it
+    // holds the words of it (r) and the block of it + 1 after its first half
+    // (q), finishes q during the first round trip -- its word 0 picks the next
+    // pair -- and draws the first half of the block of it + 2 during the
+    // second.  The byte s[k] that the next move starts from is read in the
+    // second round trip, for each of the three slots the lane can hold after
+    // the exchange (its own, the one above, the one below), and picked once
+    // the exchange is decided.  The scheduling barriers keep each half between
+    // a read and the first use of its value.  (A block split across the
+    // iteration boundary leaves two word copies per iteration where a block
+    // drawn whole two iterations ahead left six.)
+    uint32_t r[4], q[4] = {(uint32_t)(a.it_begin + 1), (uint32_t)((a.it_begin + 1) >> 32), ladder, (uint32_t)lane};
     philox4x32_10((uint32_t)a.it_begin, (uint32_t)(a.it_begin >> 32), ladder, (uint32_t)lane, k0, k1, r);
-    philox4x32_10((uint32_t)(a.it_begin + 1), (uint32_t)((a.it_begin + 1) >> 32), ladder, (uint32_t)lane, k0, k1,
-                  rn);
+    philox4x32_rounds<0, 5>(q, k0, k1);
     int k = (int)__umulhi(r[0], (uint32_t)n);
     int a_old = *lds_at(sb + k);
     // (an opaque start value for a_old: without it the compiler treats the
@@ -185,85 +192,113 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     const uint64_t it_end = a.it_end > a.it_begin ? a.it_end : a.it_begin;
     uint64_t lower = lower_mask[a.it_begin & 1];
     const uint64_t lower_flip = lower_mask[0] ^ lower_mask[1];
-    for (uint64_t ic = a.it_begin + 2; ic != it_end + 2; ++ic) {
-        // 1. move (pair k, whose current left position a_old was read ahead)
-        lds_byte* s = lds_at(sb);
-        lds_byte* occ = s + n;
-        const int d = pair_diff<V>(k);
-        const int idx = (int)__umulhi(r[1], (uint32_t)placements_of<V>(n, d));
-        const int a_new = placement<V>(n, d, idx);
-        const int b_old = a_old + d, b_new = a_new + d;
-        // the four occupancies in one round trip; the positions may coincide
-        // (a_new == a_old, a_new == b_old, b_new == a_old), which the energy
-        // change and the final counts account for in registers
-        const int o1 = occ[a_old], o2 = occ[b_old], o3 = occ[a_new], o4 = occ[b_new];
-        // 2. record the energy before the move (LDS atomic add, no read-back;
-        // each level owns its row); issued behind the reads it does not feed
-        atomicAdd(&hrow[E], hinc);
-        uint32_t c[4] = {(uint32_t)ic, (uint32_t)(ic >> 32), ladder, (uint32_t)lane};
-        __builtin_amdgcn_sched_barrier(0);
-        philox4x32_rounds<0, 5>(c, k0, k1);
-        __builtin_amdgcn_sched_barrier(0);
-        const int c3 = o3 - (a_new == a_old) - (a_new == b_old);  // after removing pair k
-        const int c4 = o4 - (b_new == a_old) - (b_new == b_old);
-        const int de = (o1 == 1) + (o2 == 1) - (c3 == 0) - (c4 == 0);
-        const bool acc = de <= 0 || r[2] < (de == 1 ? T1 : T2);
-        // final counts of the (possibly repeated) four positions, written
-        // whether or not the move is accepted (a rejected move writes back what
-        // it read); a repeated position receives the same value from every write
-        const int ac = acc ? 1 : 0;
-        occ[a_old] = (uint8_t)(o1 + ac * ((a_old == a_new) + (a_old == b_new) - 1));
-        occ[b_old] = (uint8_t)(o2 + ac * ((b_old == a_new) + (b_old == b_new) - 1));
-        occ[a_new] = (uint8_t)(acc ? c3 + 1 : o3);
-        occ[b_new] = (uint8_t)(acc ? c4 + 1 : o4);
-        s[k] = (uint8_t)(acc ? a_new : a_old);
-        E += ac * de;
-        mv_acc += ac;
-        // 3. exchange (j, j+1) with j of the iteration's parity; the threshold
-        // is read for every lane (index clamped at 0, where it is not needed),
-        // and the next move's s[k] for the three candidate slots (after the
-        // writes above, so they see this move)
-        const int E_up = from_lane_above(E);
-        const int sb_up = from_lane_above(sb);
-        const int sb_dn = from_lane_below(sb);
-        const int dx = E - E_up;
-        const uint32_t thr = trow[dx > 0 ? dx : 0];
-        const int k_next = (int)__umulhi(rn[0], (uint32_t)n);
-        const int v_own = *lds_at(sb + k_next);
-        const int v_up = *lds_at(sb_up + k_next);
-        const int v_dn = *lds_at(sb_dn + k_next);
-        __builtin_amdgcn_sched_barrier(0);
-        philox4x32_rounds<5, 10>(c, k0, k1);
-        __builtin_amdgcn_sched_barrier(0);
-        // the exchange test as lane masks: the lower lanes of this parity whose
-        // energy does not rise or whose word is under the threshold
-        const uint64_t sw_mask = lower & (__builtin_amdgcn_ballot_w64(dx <= 0) |
-                                                       __builtin_amdgcn_ballot_w64(r[3] < thr));
-        const bool sw = __builtin_amdgcn_inverse_ballot_w64(sw_mask);
-        // the upper level of an accepted exchange: the lane above a lane with
-        // sw set (the mask shifted by one lane)
-        const uint64_t up_mask = sw_mask << 1;
-        const bool upper = __builtin_amdgcn_inverse_ballot_w64(up_mask);
-        const int E_dn = from_lane_below(E);
-        E = sw ? E_up : (upper ? E_dn : E);
-        sb = sw ? sb_up : (upper ? sb_dn : sb);
-        a_old = sw ? v_up : (upper ? v_dn : v_own);
-        {
-            // up_acc += upper, the mask as the carry-in of one add
-            uint64_t carry_out;
-            asm("v_addc_co_u32_e64 %0, %1, 0, %0, %2" : "+v"(up_acc), "=s"(carry_out) : "s"(up_mask));
-        }
-        k = k_next;
-        lower ^= lower_flip;
-        // (keeps the block counter the loop's own variable, so that it is not
-        // recomputed from the iteration number at every step)
-        asm("" : "+s"(ic));
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            r[i] = rn[i];
-            rn[i] = c[i];
-        }
+    // The slot address and the energy travel together through the exchange:
+    // se = slot address << 16 | 4 E (the address is below 2^15, E at most
+    // 2n + 1, never negative), so one lane shift and one select move both,
+    // and 4 E is the byte offset of E's entry in the histogram and threshold
+    // rows.
+    int se = (sb << 16) | (E << 2);
+    const uint64_t ic_end = it_end + 2;
+    // The Philox counter words 0..2 are the block number and the ladder,
+    // shared by the wave: the parts of a block's first rounds that involve
+    // only them are drawn for a group of 64 blocks at once, one per lane, and
+    // each iteration reads its block's values from the lane that holds them
+    // (three vector reads per iteration, one value being the same for the
+    // whole group, where the scalar unit took about a dozen instructions).
+    const uint32_t l1 = (uint32_t)((uint64_t)0xCD9E8D57u * ladder) ^ (k0 + 0x9E3779B9u);
+    uint64_t ic = a.it_begin + 2;
+    while (ic != ic_end) {
+        const uint64_t gbase = ic & ~(uint64_t)63;  // this group of 64 block numbers
+        const uint64_t gb = gbase + (uint64_t)lane;
+        const PhiloxShared ug = philox4x32_shared((uint32_t)gb, (uint32_t)(gb >> 32), ladder, k0, k1);
+        const uint64_t gend = ic_end - gbase < 64 ? ic_end : gbase + 64;
+        do {
+            const int li = (int)((uint32_t)ic & 63u);
+            PhiloxShared u;
+            u.u0 = (uint32_t)__builtin_amdgcn_readlane((int)ug.u0, li);
+            u.u1 = (uint32_t)__builtin_amdgcn_readlane((int)ug.u1, li);
+            u.u2 = (uint32_t)__builtin_amdgcn_readlane((int)ug.u2, li);
+            u.u3 = (uint32_t)__builtin_amdgcn_readlane((int)ug.u3, li);
+            // 1. move (pair k, whose current left position a_old was read ahead)
+            lds_byte* s = lds_at(se >> 16);
+            lds_byte* occ = s + n;
+            const int d = pair_diff<V>(k);
+            const int idx = (int)__umulhi(r[1], (uint32_t)placements_of<V>(n, d));
+            const int a_new = placement<V>(n, d, idx);
+            const int b_old = a_old + d, b_new = a_new + d;
+            // the four occupancies in one round trip; the positions may coincide
+            // (a_new == a_old, a_new == b_old, b_new == a_old), which the energy
+            // change and the final counts account for in registers
+            const int o1 = occ[a_old], o2 = occ[b_old], o3 = occ[a_new], o4 = occ[b_new];
+            // 2. record the energy before the move (LDS atomic add, no read-back;
+            // each level owns its row); issued behind the reads it does not feed
+            atomicAdd((uint32_t*)((char*)hrow + (se & 0xffff)), hinc);  // hrow[E]
+            __builtin_amdgcn_sched_barrier(0);
+            philox4x32_rounds<5, 10>(q, k0, k1);  // the next block is complete
+            __builtin_amdgcn_sched_barrier(0);
+            const int c3 = o3 - (a_new == a_old) - (a_new == b_old);  // after removing pair k
+            const int c4 = o4 - (b_new == a_old) - (b_new == b_old);
+            const int de = (o1 == 1) + (o2 == 1) - (c3 == 0) - (c4 == 0);
+            const bool acc = de <= 0 || r[2] < (de == 1 ? T1 : T2);
+            // final counts of the (possibly repeated) four positions, written
+            // whether or not the move is accepted (a rejected move writes back what
+            // it read); a repeated position receives the same value from every write
+            const int ac = acc ? 1 : 0;
+            occ[a_old] = (uint8_t)(o1 + ac * ((a_old == a_new) + (a_old == b_new) - 1));
+            occ[b_old] = (uint8_t)(o2 + ac * ((b_old == a_new) + (b_old == b_new) - 1));
+            occ[a_new] = (uint8_t)(acc ? c3 + 1 : o3);
+            occ[b_new] = (uint8_t)(acc ? c4 + 1 : o4);
+            s[k] = (uint8_t)(acc ? a_new : a_old);
+            se += (ac * de) << 2;
+            mv_acc += ac;
+            // 3. exchange (j, j+1) with j of the iteration's parity; the threshold
+            // is read for every lane (index clamped at 0, where it is not needed),
+            // and the next move's s[k] for the three candidate slots (after the
+            // writes above, so they see this move)
+            const int se_up = from_lane_above(se);
+            const int se_dn = from_lane_below(se);
+            const int dx4 = (se & 0xffff) - (se_up & 0xffff);  // 4 (E - E_up)
+            const uint32_t thr = *(const uint32_t*)((const char*)trow + (dx4 > 0 ? dx4 : 0));
+            const int k_next = (int)__umulhi(q[0], (uint32_t)n);
+            const int v_own = *lds_at((se >> 16) + k_next);
+            const int v_up = *lds_at((se_up >> 16) + k_next);
+            const int v_dn = *lds_at((se_dn >> 16) + k_next);
+            uint32_t c[4];
+            __builtin_amdgcn_sched_barrier(0);
+            philox4x32_first4(u, l1, (uint32_t)lane, k1, c);  // the block after next, first half
+            philox4x32_rounds<4, 5>(c, k0, k1);
+            __builtin_amdgcn_sched_barrier(0);
+            // the exchange test as lane masks: the lower lanes of this parity whose
+            // energy does not rise or whose word is under the threshold
+            const uint64_t sw_mask =
+                lower & (__builtin_amdgcn_ballot_w64(dx4 <= 0) | __builtin_amdgcn_ballot_w64(r[3] < thr));
+            const bool sw = __builtin_amdgcn_inverse_ballot_w64(sw_mask);
+            // the upper level of an accepted exchange: the lane above a lane with
+            // sw set (the mask shifted by one lane)
+            const uint64_t up_mask = sw_mask << 1;
+            const bool upper = __builtin_amdgcn_inverse_ballot_w64(up_mask);
+            se = sw ? se_up : (upper ? se_dn : se);
+            a_old = sw ? v_up : (upper ? v_dn : v_own);
+            {
+                // up_acc += upper, the mask as the carry-in of one add
+                uint64_t carry_out;
+                asm("v_addc_co_u32_e64 %0, %1, 0, %0, %2" : "+v"(up_acc), "=s"(carry_out) : "s"(up_mask));
+            }
+            k = k_next;
+            lower ^= lower_flip;
+    #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                r[i] = q[i];
+                q[i] = c[i];
+            }
+            // (the loop tests the incremented block counter itself, so that it is
+            // neither recomputed from the iteration number nor copied)
+            ++ic;
+            asm("" : "+s"(ic));
+        } while (ic != gend);
     }
+    E = (se & 0xffff) >> 2;
+    sb = (int)((uint32_t)se >> 16);
     const uint32_t sw_acc = (uint32_t)from_lane_above((int)up_acc);
     __syncthreads();
 
@@ -275,7 +310,7 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
         a.energy_out[(size_t)ladder * M + lane] = E;
         const lds_byte* s = lds_at(sb);
         uint8_t* dst = a.state_out + ((size_t)ladder * M + lane) * n;
-        for (int k = 0; k < n; ++k) dst[k] = s[k];
+        for (int k = 0; k < n; ++k) dst[k] = (uint8_t)(s[k] + 1);
     }
 }
 
