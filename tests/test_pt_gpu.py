@@ -55,6 +55,24 @@ def test_segments_carry_the_chains():
     assert a["hist"][1] == o["hist"] and a["state"][1] == o["final_a"]
 
 
+@pytest.mark.parametrize("variant,segment", [("skolem", 1), ("langford", 2), ("skolem", 63), ("hooked", 64),
+                                             ("skolem", 65)])
+def test_segment_lengths_around_the_philox_groups(variant, segment):
+    """The kernel draws the wave-shared parts of the Philox blocks for 64
+    block numbers at a time: launches of any length (one iteration, fewer than
+    64, exactly 64, one more), starting anywhere inside such a group, continue
+    the same chains as the oracle's single run."""
+    betas = [0.0, 0.5, 1.5, 3.0, 6.0]
+    iters, seed = 200, 4242
+    _say("pt segments", variant, segment)
+    g = sk.pt_run(9, variant, betas, 2, iters, seed, segment=segment)
+    for lad in range(2):
+        o = O.pt_ladder(9, variant, betas, iters, seed, ladder=lad, schedule="even_odd")
+        assert g["hist"][lad] == o["hist"]
+        assert g["move_accept"][lad] == o["move_accept"]
+        assert g["state"][lad] == o["final_a"] and g["energy"][lad] == o["final_e"]
+
+
 def test_max_levels_and_size():
     betas = [0.0] + [0.05 * (120 ** (j / 62)) for j in range(63)]
     g = sk.pt_run(32, "skolem", betas, 1, 300, 5)
