@@ -197,6 +197,8 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     // 2n + 1, never negative), so one lane shift and one select move both,
     // and 4 E is the byte offset of E's entry in the histogram and threshold
     // rows.
+    static_assert(64 * (kPtMaxN + (2 * kPtMaxN + 2) + 3) < (1 << 15) && 4 * (2 * kPtMaxN + 1) < (1 << 16),
+                  "the 64 slots (the kernel declares no other LDS before them) and 4 E must fit their halves");
     int se = (sb << 16) | (E << 2);
     const uint64_t ic_end = it_end + 2;
     // The Philox counter words 0..2 are the block number and the ladder,
