@@ -98,7 +98,9 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     const int n = a.n;
     const int top = a.top;
     const int H = top + 1;
-    const int slot_bytes = a.slot_bytes;  // n placements + (top + 1) occupancies, rounded to 4
+    // n placements, then the occupancies of positions 1..top at bytes 0..top-1 (the host sizes
+    // top + 1 of them), rounded to 4
+    const int slot_bytes = a.slot_bytes;
     uint32_t* hist = (uint32_t*)(lds + (size_t)64 * slot_bytes);  // M x H
     uint32_t* swap_thr = hist + M * H;                              // M x H, copy of a.swap_thr
     const bool live = lane < M;
