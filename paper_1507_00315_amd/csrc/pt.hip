@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     const int top = a.top;
     const int H = top + 1;
     // n placements, then the occupancies of positions 1..top at bytes 0..top-1 (the host sizes
-    // top + 1 of them), rounded to 4
+    // top + 1 of them), rounded to an odd number of 4-byte words
     const int slot_bytes = a.slot_bytes;
     uint32_t* hist = (uint32_t*)(lds + (size_t)64 * slot_bytes);  // M x H
     uint32_t* swap_thr = hist + M * H;                              // M x H, copy of a.swap_thr
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     // 2n + 1, never negative), so one lane shift and one select move both,
     // and 4 E is the byte offset of E's entry in the histogram and threshold
     // rows.
-    static_assert(64 * (kPtMaxN + (2 * kPtMaxN + 2) + 3) < (1 << 15) && 4 * (2 * kPtMaxN + 1) < (1 << 16),
+    static_assert(64 * (kPtMaxN + (2 * kPtMaxN + 2) + 3 + 4) < (1 << 15) && 4 * (2 * kPtMaxN + 1) < (1 << 16),
                   "the 64 slots (the kernel declares no other LDS before them) and 4 E must fit their halves");
     int se = (sb << 16) | (E << 2);
     const uint64_t ic_end = it_end + 2;

@@ -181,7 +181,11 @@ static sk_status pt_run_impl(const Relaxed& R, const sk_pt_params* p, hipStream_
     const std::vector<float> beta_f(p->beta, p->beta + M);
     PtDevice D;
     const size_t nst = (size_t)Lad * M * n, nh = (size_t)Lad * M * H, nl = (size_t)Lad * M;
-    const int slot_bytes = (n + H + 3) & ~3;
+    // an odd number of LDS words per slot: the lanes' byte accesses at the same offset in
+    // their slots spread over the banks (an even stride, 16 words at n = 20, made S(20)
+    // 2 % slower)
+    int slot_bytes = (n + H + 3) & ~3;
+    if ((slot_bytes / 4) % 2 == 0) slot_bytes += 4;
     // LDS: 64 configuration slots, the histograms and the exchange thresholds
     const size_t lds = (size_t)64 * slot_bytes + 2 * (size_t)M * H * sizeof(uint32_t);
     // iterations per launch; LDS counters stay below 2^32
