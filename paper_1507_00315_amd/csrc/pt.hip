@@ -88,6 +88,22 @@ __device__ __forceinline__ lds_byte* lds_at(int addr)
     return (lds_byte*)(uintptr_t)(uint32_t)addr;
 }
 
+// Layout of the 64 configuration slots in LDS, chosen per variant by
+// measurement: rows (a slot's bytes adjacent, slots slot_bytes apart) or
+// columns (element i of every slot adjacent: byte base + 64 i of the slot).
+// The LDS bank conflicts of the lanes' byte accesses depend on the layout and
+// on the chains' positions: columns made the Langford chains 7 % faster, the
+// Skolem chains 2.5 % and the hooked chains 4 % slower.
+template <int V>
+constexpr int kSlotShift = V == 1 ? 6 : 0;
+
+// One byte array of a configuration slot: element i at byte base + (i << SHIFT).
+template <int SHIFT>
+struct SlotBytes {
+    int base;
+    __device__ __forceinline__ lds_byte& operator[](int i) const { return *lds_at(base + (i << SHIFT)); }
+};
+
 template <int V>
 __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
 {
@@ -118,7 +134,8 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     // LDS address of the lane's current slot (the address itself, not an
     // offset from the array, so that the slot moves between lanes as a plain
     // value and its bytes are addressed without an add per access)
-    int sb = (int)(uint32_t)(uintptr_t)(lds_byte*)lds + lane * slot_bytes;
+    constexpr int SH = kSlotShift<V>;
+    int sb = (int)(uint32_t)(uintptr_t)(lds_byte*)lds + (SH ? lane : lane * slot_bytes);
     int E = 0;
     // accepted moves; accepted exchanges counted at the upper level of the
     // pair (a lane mask the scalar unit forms), moved to the lower level
@@ -139,8 +156,7 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     uint64_t lower_mask[2] = {0, 0};
     for (int j = 0; j + 1 < M; ++j) lower_mask[j & 1] |= 1ull << j;
     {
-        lds_byte* s = lds_at(sb);
-        lds_byte* occ = s + n;
+        const SlotBytes<SH> s{sb}, occ{sb + (n << SH)};
         for (int p = 0; p <= top; ++p) occ[p] = 0;
         if (live && a.state_in) {
             const uint8_t* src = a.state_in + ((size_t)ladder * M + lane) * n;
@@ -184,7 +200,7 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
     philox4x32_10((uint32_t)a.it_begin, (uint32_t)(a.it_begin >> 32), ladder, (uint32_t)lane, k0, k1, r);
     philox4x32_rounds<0, 5>(q, k0, k1);
     int k = (int)__umulhi(r[0], (uint32_t)n);
-    int a_old = *lds_at(sb + k);
+    int a_old = *lds_at(sb + (k << SH));
     // (an opaque start value for a_old: without it the compiler treats the
     // loop's a_old as a byte, and the iteration takes one instruction more)
     asm("" : "+v"(a_old));
@@ -224,8 +240,7 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
             u.u2 = (uint32_t)__builtin_amdgcn_readlane((int)ug.u2, li);
             u.u3 = (uint32_t)__builtin_amdgcn_readlane((int)ug.u3, li);
             // 1. move (pair k, whose current left position a_old was read ahead)
-            lds_byte* s = lds_at(se >> 16);
-            lds_byte* occ = s + n;
+            const SlotBytes<SH> s{se >> 16}, occ{(se >> 16) + (n << SH)};
             const int d = pair_diff<V>(k);
             const int idx = (int)__umulhi(r[1], (uint32_t)placements_of<V>(n, d));
             const int a_new = placement<V>(n, d, idx);
@@ -264,9 +279,9 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
             const int dx4 = (se & 0xffff) - (se_up & 0xffff);  // 4 (E - E_up)
             const uint32_t thr = *(const uint32_t*)((const char*)trow + (dx4 > 0 ? dx4 : 0));
             const int k_next = (int)__umulhi(q[0], (uint32_t)n);
-            const int v_own = *lds_at((se >> 16) + k_next);
-            const int v_up = *lds_at((se_up >> 16) + k_next);
-            const int v_dn = *lds_at((se_dn >> 16) + k_next);
+            const int v_own = *lds_at((se >> 16) + (k_next << SH));
+            const int v_up = *lds_at((se_up >> 16) + (k_next << SH));
+            const int v_dn = *lds_at((se_dn >> 16) + (k_next << SH));
             uint32_t c[4];
             __builtin_amdgcn_sched_barrier(0);
             philox4x32_first4(u, l1, (uint32_t)lane, k1, c);  // the block after next, first half
@@ -312,7 +327,7 @@ __global__ void __launch_bounds__(64) pt_ladder_kernel(const PtArgs a)
         a.move_acc[(size_t)ladder * M + lane] += mv_acc;
         a.swap_acc[(size_t)ladder * M + lane] += sw_acc;
         a.energy_out[(size_t)ladder * M + lane] = E;
-        const lds_byte* s = lds_at(sb);
+        const SlotBytes<SH> s{sb};
         uint8_t* dst = a.state_out + ((size_t)ladder * M + lane) * n;
         for (int k = 0; k < n; ++k) dst[k] = (uint8_t)(s[k] + 1);
     }
