@@ -80,10 +80,10 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # (kernel, workload or leg, log2 sign vectors per work item, waves per launch):
     #     (fingerprint, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("exact_batch_kernel", "batch", 22, 6144): ("30f4c6bb20835127", 1216.9375, 13246.5625),
-    ("exact_batch_kernel", "batch", 22, 8192): ("30f4c6bb20835127", 1216.8125, 13312.15625),
-    ("exact_v2_kernel", "skolem:24 slice", 26, 8192): ("fcb120309dc22ca1", 619.5625, 24832.0),
-    ("exact_v2_kernel", "langford:24 slice", 26, 8192): ("fcb120309dc22ca1", 617.0625, 24832.0),
+    ("exact_batch_kernel", "batch", 22, 6144): ("30f4c6bb20835127", 1247.125, 13246.46875),
+    ("exact_batch_kernel", "batch", 22, 8192): ("30f4c6bb20835127", 1249.1875, 13311.375),
+    ("exact_v2_kernel", "skolem:24 slice", 26, 8192): ("fcb120309dc22ca1", 628.9375, 24832.0),
+    ("exact_v2_kernel", "langford:24 slice", 26, 8192): ("fcb120309dc22ca1", 613.1875, 24832.0),
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
